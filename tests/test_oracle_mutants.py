@@ -1,0 +1,53 @@
+"""The pins are strong enough: each plausible mistake planted in a copy of the
+oracle (on the CPU) makes at least one pin test fail.
+
+Every mutant is one textual change of ``oracle/hydro_oracle.c`` (a dropped
+term, a wrong sign, index or operand), compiled into a temporary library that
+the pin tests load through ``HYDRO_ORACLE_LIB`` in a child pytest process.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
+PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py"]
+
+MUTANTS = {
+    "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
+    "hllc-star-energy-sign": ("(Ss + pL / (rL * (SL - uL)))", "(Ss - pL / (rL * (SL - uL)))"),
+    "hllc-contact-speed-sign": ("double Ss = (pR - pL +", "double Ss = (pL - pR +"),
+    "hllc-davis-drops-right": ("double SL = fmin(uL - cL, uR - cR);", "double SL = uL - cL;"),
+    "hllc-energy-flux-drops-p": ("uR * (ER + pR)};", "uR * ER};"),
+    "hllc-tangential-star": ("a * Ss, a * vR, a * wR,", "a * Ss, a * vL, a * wR,"),
+    "plm-right-state-sign": ("wr[v] = w2 - 0.5 *", "wr[v] = w2 + 0.5 *"),
+    "plm-wrong-slope-pair": ("oracle_minmod(w2 - w1, w3 - w2)", "oracle_minmod(w1 - w0, w3 - w2)"),
+    "minmod-picks-larger": ("if (a > 0.0 && b > 0.0) return a < b ? a : b;", "if (a > 0.0 && b > 0.0) return a > b ? a : b;"),
+    "recovery-drops-w-term": ("0.5 * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3])", "0.5 * (U[1] * W[1] + U[2] * W[2])"),
+    "guard-neighbour-off-by-one": ("sc = side ? layer - 1 : nsrc - layer;", "sc = side ? layer : nsrc - layer;"),
+    "guard-outflow-wrong-layer": ("sc = side ? n[axis] - 1 : 0;", "sc = side ? n[axis] - 2 : 0;"),
+    "rotation-not-swapped-back": ("f[1] = f[1 + d];\n          f[1 + d] = t;", "(void)t;"),
+    "rk2-drops-un": ("Uout[a] = 0.5 * Un[a] + 0.5 * (src + d);", "Uout[a] = src + 0.5 * d;"),
+    "cfl-uses-x-velocity": ("lam += (fabs(W[1 + d]) + c) / dx[d];", "lam += (fabs(W[1]) + c) / dx[d];"),
+    "update-wrong-face": ("hi[d] += 1;", "hi[d] += 0;"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name} not unique"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    env = dict(os.environ, HYDRO_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived every pin:\n{r.stdout[-2000:]}"
