@@ -22,6 +22,13 @@ from paper_2507_09337_amd import inputs
 RNG = np.random.default_rng(12345)
 
 
+@pytest.fixture(autouse=True)
+def _reseed(request):
+    """Each test draws from its own seeded stream, whatever the test order."""
+    global RNG
+    RNG = np.random.default_rng(sum(map(ord, request.node.name)))
+
+
 def euler_flux(W, gamma):
     """Physical Euler flux along the first velocity component, from its definition."""
     r, u, v, w, p = W
@@ -169,11 +176,15 @@ def test_hllc_star_state_contact_structure():
     star state must move with S*, carry side K's tangential velocities, and
     the flux must have the contact form F = S* U*_K + p* (0, 1, 0, 0, S*)."""
     gamma = 1.4
+    checked = 0
     for _ in range(2000):
         WL, WR = rand_state(), rand_state()
         cL, cR = math.sqrt(gamma * WL[4] / WL[0]), math.sqrt(gamma * WR[4] / WR[0])
-        SL = min(WL[1] - cL, WR[1] - cR)  # Davis bounds; subsonic data put 0 strictly inside
+        SL = min(WL[1] - cL, WR[1] - cR)  # Davis bounds
         SR = max(WL[1] + cL, WR[1] + cR)
+        if not (SL < 0.0 < SR):  # a supersonic pair has no star state at the face
+            continue
+        checked += 1
         # p_L + aL (S - u_L) = p_R + aR (S - u_R), a_K = rho_K (S_K - u_K)
         aL, aR = WL[0] * (SL - WL[1]), WR[0] * (SR - WR[1])
         s_star = (WR[4] - WL[4] + aL * WL[1] - aR * WR[1]) / (aL - aR)
@@ -187,6 +198,7 @@ def test_hllc_star_state_contact_structure():
         assert Us[3] / Us[0] == pytest.approx(W[3], rel=1e-10, abs=1e-12)
         want = s_star * Us + p_star * np.array([0.0, 1.0, 0.0, 0.0, s_star])
         assert np.allclose(F, want, rtol=1e-10, atol=1e-11 * scale)
+    assert checked >= 1500
 
 
 # ---------------------------------------------------------------- recovery
