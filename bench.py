@@ -1,0 +1,247 @@
+"""Benchmark of the hydro packet step on one MI355X.
+
+Workload (default): the large FP32-bulk run -- 32768 blocks of 16^3 cells on
+the periodic unit cube (512^3 cells), Sedov deposit plus 1 % density noise,
+gamma 1.4, CFL 0.4.  One "step" is one full SSP-RK2 step of the whole mesh.
+
+Timed paths (same input, state reset between them):
+  * batched mixed  -- all 512 packets of 64 blocks in one persistent launch per
+                      RK stage, one HIP graph per step, dt on the device;
+                      FP32 PLM + HLLC, FP64 recovery/accumulation/state.  This
+                      is the headline `value`.
+  * batched FP64   -- the same with every operation in FP64.
+  * plain FP64     -- per-packet launches per stage (512 packets of 64
+                      blocks) and a host reduce_dt per packet each step.
+
+Metric: cell-updates/s (interior cells x steps / wall time, inputs resident in
+HBM).  Roofline: HBM, 200 algorithmic bytes per cell-update (FP64 state, five
+state passes: stage 1 reads Un and writes U1, stage 2 reads U1 and Un and
+writes Un+1), 8.0 TB/s peak; the stage kernel's launch durations are measured
+with HIP events on the mesh stream.  Errors vs the FP64 oracle are measured on
+sampled blocks after one step from the initial state.  cpu_baseline: the
+oracle (plain FP64 C, OpenMP) on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|smooth|uneven|sedov]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s and % HBM roofline, FP32-batched vs FP64-plain, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_UPDATE = 200.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(name: str):
+    from paper_2507_09337_amd import inputs as I
+
+    if name == "large":
+        return I.sedov_noise()
+    if name == "smooth":
+        return I.smooth3d()
+    if name == "uneven":
+        return I.uneven()
+    if name == "sedov":
+        return I.sedov3d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sample_blocks(P, k=6):
+    nb = P.mesh.nblocks
+    rng = np.random.default_rng(0)
+    ids = set(rng.choice(nb, size=min(k, nb), replace=False).tolist())
+    sub = P.meta.get("subset")
+    if sub is not None:  # include a block at the blast centre
+        ids.add(int(sub[len(sub) // 2]))
+    return sorted(ids)
+
+
+def one_step_errors(P, arena, U0_dev, mesh, packets_fp64, packets_mixed):
+    """Error of one step from the initial state vs the oracle on sampled blocks."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2507_09337_amd import hydro as H
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import l1_rho, rel_err
+
+    ids = sample_blocks(P)
+    dt = O.dt(P.mesh, P.U0, P.gamma, P.cfl)
+    ref = O.step_subset(P.mesh, P.U0, dt, P.gamma, ids)
+    out = {}
+    for name, pks in (("fp64", packets_fp64), ("mixed", packets_mixed)):
+        arena.copy_(U0_dev)
+        b = H.Batch(pks)
+        b.run(1, P.cfl, P.gamma)
+        b.close()
+        torch.cuda.synchronize()
+        U = np.empty_like(P.U0)
+        for i in ids:  # copy back only the sampled blocks
+            o, n = int(P.mesh.offset[i]), 5 * int(P.mesh.ncells[i])
+            U[o:o + n] = arena[o:o + n].cpu().numpy()
+        out[name] = {"max_rel_err": rel_err(P.mesh, U, ref, ids), "l1_rho_rel": l1_rho(P.mesh, U, ref, ids)}
+    out["sample_blocks"] = len(ids)
+    return out
+
+
+def cpu_baseline(P, budget_s=12.0):
+    """The oracle as it stands, on the 8x8x8-block cube at the centre of the
+    workload (or the first 512 blocks), steps until ~budget_s of CPU work."""
+    from oracle import oracle as O
+
+    sub = P.meta.get("subset")
+    ids = sub if sub is not None else np.arange(min(512, P.mesh.nblocks))
+    m = P.mesh.subset(ids)
+    U = P.mesh.gather(P.U0, ids)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < 50:
+        dt = O.dt(m, U, P.gamma, P.cfl)
+        O.step(m, U, dt, P.gamma)
+        steps += 1
+    el = time.perf_counter() - t0
+    cells = m.total_cells
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{len(ids)} blocks ({cells} cells) of the workload as their own periodic mesh, {steps} steps, "
+                      f"{el:.1f} s, dt from the sample each step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-packet FP64 path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tune", action="store_true", help="autotune the batched launches first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from oracle import oracle as O
+    from paper_2507_09337_amd import hydro as H
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    P = make_problem(args.workload)
+    cells = P.mesh.total_cells
+    log(f"workload {P.name}: {P.mesh.nblocks} blocks, {cells} cells, built in {time.perf_counter() - t0:.1f} s")
+
+    U0_dev = torch.from_numpy(P.U0).to("cuda")
+    arena = torch.empty_like(U0_dev)
+    arena.copy_(U0_dev)
+    mesh = H.Mesh(P.mesh, arena)
+    pk64 = [H.Packet(mesh, ids, H.FP64) for ids in P.packets]
+    pkmx = [H.Packet(mesh, ids, H.FP32_FP64) for ids in P.packets]
+    log(f"{len(P.packets)} packets")
+
+    errs = one_step_errors(P, arena, U0_dev, mesh, pk64, pkmx)
+    log("one-step errors vs oracle:", json.dumps(errs))
+
+    results = {}
+    kernel_ms = {}
+    for name, pks in (("batched_mixed", pkmx), ("batched_fp64", pk64)):
+        arena.copy_(U0_dev)
+        b = H.Batch(pks)
+        if args.tune:
+            b.autotune(P.gamma, reps=3)
+        b.run(args.warmup, P.cfl, P.gamma)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        b.run(args.steps, P.cfl, P.gamma)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        results[name] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                         "config": b.config()}
+        arena.copy_(U0_dev)
+        kernel_ms[name] = b.time_kernels(args.steps, P.cfl, P.gamma)
+        b.close()
+        log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
+
+    if not args.no_plain:
+        arena.copy_(U0_dev)
+        b = H.Batch(pk64)
+
+        def plain_step():
+            dt = min(pk.reduce_dt(P.gamma, P.cfl) for pk in pk64)
+            b.advance_plain(dt, P.gamma)
+
+        for _ in range(args.warmup):
+            plain_step()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            plain_step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        results["plain_fp64"] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps}
+        b.close()
+        log("plain_fp64", json.dumps(results["plain_fp64"]))
+
+    head = results["batched_mixed"]
+    km = kernel_ms["batched_mixed"]
+    stage_ms = km["stage1_ms"] + km["stage2_ms"]
+    achieved = BYTES_PER_CELL_UPDATE * cells / (stage_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None,
+        "kernel": "k_stage (stage-1 + stage-2 launch of one step; 80 + 120 algorithmic B per interior cell)",
+        "stage1_ms": km["stage1_ms"], "stage2_ms": km["stage2_ms"],
+        "algorithmic_bytes_per_step": BYTES_PER_CELL_UPDATE * cells,
+    }
+    km64 = kernel_ms["batched_fp64"]
+    ach64 = BYTES_PER_CELL_UPDATE * cells / ((km64["stage1_ms"] + km64["stage2_ms"]) * 1e-3) / 1e9
+
+    cpu = None if args.no_cpu else cpu_baseline(P)
+    if cpu:
+        log("cpu_baseline", json.dumps(cpu))
+
+    line = {
+        "metric": METRIC,
+        "value": head["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (PLM+HLLC) / f64 (state, recovery, update, dt)",
+        "data": "synthetic (seeded)",
+        "config": {"workload": f"{P.name}: {P.mesh.nblocks} blocks of {int(P.mesh.n[0, 0])}^3, {cells} cells, "
+                               f"{len(P.packets)} packets, periodic, gamma {P.gamma}, CFL {P.cfl}",
+                   "path": "batched mixed FP32/FP64, persistent launch per stage, HIP graph per step",
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paths": {k: {kk: vv for kk, vv in v.items() if kk != "config"} for k, v in results.items()},
+        "batched_fp64_roofline_frac": ach64 / HBM_PEAK_GBS,
+        "tuning": results["batched_mixed"]["config"],
+        "errors_vs_oracle_one_step": errs,
+    }
+    if "plain_fp64" in results:
+        line["speedup_vs_plain_fp64"] = head["cell_updates_per_s"] / results["plain_fp64"]["cell_updates_per_s"]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

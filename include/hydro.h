@@ -1,0 +1,214 @@
+/*
+ * hydro.h -- C ABI of the MI355X hydro packet library (libhydro.so).
+ *
+ * The library applies one explicit finite-volume compressible-Euler step to a
+ * packet of mesh blocks on one GPU: guard cells, PLM reconstruction with the
+ * minmod limiter, HLLC fluxes, a conservative SSP-RK2 update, and a CFL time
+ * step reduction.  This is the per-block physics task that ORCHA (arXiv
+ * 2507.09337) maps onto the GPU:
+ *   - Sec. 4 (Code Generators): a TaskFunction is the group of API functions a
+ *     device runs together; its DataItem, when it runs on a device, is a
+ *     DataPacket that carries everything the TaskFunction needs;
+ *   - Sec. 4.3 (DataItem Generators): a DataPacket concatenates n AMR blocks,
+ *     n chosen at run time, because single blocks are too small to use a GPU;
+ *   - Sec. 4 (static-code requirements): the code is thread safe, never
+ *     allocates scratch space itself (it is handed in), and keeps no
+ *     non-constant globals;
+ *   - Sec. 5.1 (Flash-X): blocks hold equal numbers of equally sized cells;
+ *   - Sec. 5.2 (Sedov): ideal-gas gamma-law equation of state;
+ *   - Sec. 6 (Experiments): explicit finite volume with a guard-cell halo,
+ *     2nd-order Runge-Kutta with a guard refresh before each stage.
+ * Reconstruction, Riemann solver and time-step rule are not given by the paper
+ * and follow the textbook methods: PLM (van Leer 1979) on primitive variables
+ * with minmod (Roe 1986); HLLC (Toro, Spruce & Speares 1994) with Davis
+ * wave speeds; SSP-RK2 (Shu & Osher 1988); dt = CFL / max_c sum_d (|u_d|+c)/dx_d.
+ *
+ * Conventions for every call
+ *   - Every call returns a hydro_status; HYDRO_OK is 0.  No exception or
+ *     signal crosses the ABI.  On failure hydro_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Arguments are checked on the host before any device call; a rejected
+ *     call has no effect.  Descriptor errors are HYDRO_EINVAL and are reported
+ *     without touching a GPU.
+ *   - Pointers named "device" point to GPU memory of the current HIP device;
+ *     all others are host pointers, read during the call only.
+ *   - Work is enqueued on the stream given at mesh creation (a hipStream_t;
+ *     NULL is the default stream) and is stream-ordered; only calls documented
+ *     as synchronising wait for the GPU.
+ *   - Handles are not thread safe: concurrent calls on one mesh (or on
+ *     packets/batches of one mesh) must be serialised by the caller.
+ *
+ * State layout (the "arena", owned by the caller, FP64):
+ *   block b, conserved variable v (0 rho, 1 rho*u, 2 rho*v, 3 rho*w, 4 E),
+ *   interior cell (i, j, k) with i fastest:
+ *       arena[offset_b + v * nx*ny*nz + (k*ny + j)*nx + i].
+ *   Blocks store interior cells only.  Guard values are gathered from the
+ *   neighbour blocks' interiors by the kernels when they load a tile, so the
+ *   arena needs no guard storage.  In 2D, nz == 1 and rho*w must be 0.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HYDRO_OK = 0,
+  HYDRO_EINVAL = 1,   /* bad argument or descriptor; nothing was done          */
+  HYDRO_EDEVICE = 2,  /* a HIP runtime call failed (message names it)          */
+  HYDRO_ENOMEM = 3,   /* device or host allocation failed                       */
+  HYDRO_ENONPHYS = 4, /* a state with rho <= 0, p <= 0 or a non-finite value  */
+  HYDRO_ESTATE = 5    /* call not valid in this state (e.g. packet not closed) */
+} hydro_status;
+
+typedef enum {
+  HYDRO_FP64 = 0,     /* every operation in FP64                                         */
+  HYDRO_FP32_FP64 = 1 /* FP64 state, recovery, accumulation and dt; PLM + HLLC in FP32   */
+} hydro_precision;
+
+typedef enum {
+  HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
+  HYDRO_OUTFLOW = 1,      /* zero gradient: both guard layers copy the edge layer        */
+  HYDRO_PERIODIC_SELF = 2 /* wrap around the block itself                                 */
+} hydro_face_kind;
+
+/* One mesh block (Sec. 5.1: a block of equally sized cells).  Faces are
+ * ordered -x, +x, -y, +y, -z, +z.  A HYDRO_NBR face must name a block whose
+ * extents along the two tangential axes equal this block's.  In 2D the z
+ * faces are ignored.  Interior extents: n[0] and n[1] multiples of 8 (the
+ * kernels tile x-y planes in 8x8 or 16x16 tiles), n[2] >= 2 in 3D and == 1 in
+ * 2D, n[0]*n[1]*n[2] < 2^31. */
+typedef struct {
+  int32_t n[3];         /* interior cells per axis                                  */
+  int32_t face_kind[6]; /* hydro_face_kind per face                                  */
+  int32_t nbr[6];       /* neighbour block id (0..nblocks-1) of HYDRO_NBR faces      */
+  int32_t reserved;     /* must be 0                                                 */
+  int64_t offset;       /* element offset of variable 0 of this block in the arena   */
+  double dx[3];         /* cell widths (> 0); dx[2] ignored in 2D                     */
+} hydro_block_desc;
+
+typedef struct hydro_mesh hydro_mesh;     /* block table + arena + scratch (U1, accumulators) */
+typedef struct hydro_packet hydro_packet; /* an ordered list of blocks of one mesh (DataPacket) */
+typedef struct hydro_batch hydro_batch;   /* packets advanced stage-synchronously together      */
+
+/* Create a mesh over a caller-owned device arena of arena_len doubles.
+ * blocks: host array of nblocks descriptors (copied).  ndim: 2 or 3.
+ * Block ranges [offset, offset + 5*ncell) must lie inside the arena and must
+ * not overlap.  stream: hipStream_t used for all work on this mesh.
+ * Allocates the mesh's device scratch (one arena-sized FP64 buffer for the
+ * first RK stage, the block table and accumulators) on the current device;
+ * no later call allocates device memory except packet/batch creation (work
+ * lists) and the first hydro_batch_run (graph instantiation).
+ * Errors: EINVAL (descriptor, overlap, extents), ENOMEM, EDEVICE. */
+hydro_status hydro_mesh_create(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *arena,
+                               int64_t arena_len, void *stream, hydro_mesh **out);
+
+/* Destroy a mesh.  Packets and batches of the mesh must be destroyed first
+ * (HYDRO_ESTATE otherwise).  Synchronises the mesh stream. */
+hydro_status hydro_mesh_destroy(hydro_mesh *m);
+
+/* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
+ * listed blocks of mesh m, advanced in the given hydro_precision.  block_ids:
+ * host array of nblocks distinct ids.  Builds the packet's device work list.
+ * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
+ * EDEVICE. */
+hydro_status hydro_packet_create(hydro_mesh *m, const int32_t *block_ids, int32_t nblocks, int32_t precision,
+                                 hydro_packet **out);
+
+/* One full SSP-RK2 step of the packet with time step dt and ratio of
+ * specific heats gamma, in place on the arena (Sec. 6: explicit finite volume,
+ * 2nd-order Runge-Kutta, guards refreshed before each stage):
+ *   U1 = Un + dt L(Un);  Un+1 = Un/2 + (U1 + dt L(U1))/2.
+ * Only interior cells of the packet's blocks are written.  Stage 2 needs the
+ * first-stage values of every face neighbour, so the packet must be closed
+ * (every HYDRO_NBR face of its blocks names a block of the packet); otherwise
+ * HYDRO_ESTATE (use hydro_batch_advance_plain or hydro_batch_run, which keep
+ * the stages synchronous across packets).  Asynchronous.  The stage-2 kernel
+ * also reduces the CFL rate of the new state for hydro_packet_reduce_dt.
+ * Errors: EINVAL (dt or gamma not finite and > 0, gamma <= 1), ESTATE, EDEVICE. */
+hydro_status hydro_packet_advance(hydro_packet *p, double dt, double gamma);
+
+/* dt = cfl / max over the packet's interior cells of sum_d (|u_d| + c)/dx_d,
+ * c = sqrt(gamma p / rho), computed in FP64 on the device.  If the last call
+ * on this packet was an advance with the same gamma, the rate it reduced is
+ * used; otherwise the arena is read again.  (A caller that writes the arena
+ * between an advance and this call must pass a different gamma or create a
+ * new packet.)  Synchronising.  HYDRO_ENONPHYS if any state touched by the
+ * last advance, or any interior state now, has rho <= 0, p <= 0 or a
+ * non-finite value (the message names a block).
+ * Errors: EINVAL (cfl or gamma), ENONPHYS, EDEVICE. */
+hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, double *dt_out);
+
+hydro_status hydro_packet_destroy(hydro_packet *p);
+
+/* A batch of packets of one mesh (all packets must share the mesh and the
+ * precision; a block may appear in at most one packet of the batch).  Builds the concatenated device work
+ * list used by the persistent batched launches.  Errors: EINVAL, ENOMEM,
+ * EDEVICE. */
+hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, hydro_batch **out);
+
+/* One SSP-RK2 step of every packet with per-packet launches: stage 1 of every
+ * packet, then stage 2 of every packet (stage-synchronous, so packets need
+ * not be closed).  Each packet then holds its reduced CFL rate for
+ * hydro_packet_reduce_dt.  Asynchronous.  Errors: EINVAL, EDEVICE. */
+hydro_status hydro_batch_advance_plain(hydro_batch *b, double dt, double gamma);
+
+/* nsteps SSP-RK2 steps of the whole batch with dt = cfl / max rate taken
+ * from the state at the start of each step and kept on the device: one
+ * persistent launch per RK stage over the concatenated work list of all
+ * packets, one captured HIP graph per step, replayed nsteps times with no
+ * host synchronisation in between.  Synchronising.  *t_out (host, may be
+ * NULL) receives the simulated time advanced.  The first call with a given
+ * (cfl, gamma) instantiates the graph.
+ * Errors: EINVAL, ENONPHYS (the state became non-physical; the arena then
+ * holds the state of the failing step), EDEVICE. */
+hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out);
+
+hydro_status hydro_batch_destroy(hydro_batch *b);
+
+/* Launch configuration of the batched path and its autotuner (Sec. 7 of the
+ * paper lists auto-tuned kernel generation as future work; here a tuner picks
+ * among compiled tilings by timing them).  Blocks are grouped into classes by
+ * edge length (n[0] when n[0] == n[1] (== n[2] in 3D), else class 0).  Per
+ * class the tiling is:
+ *   tile:   0 = 16x16 tiles, one per 256-thread workgroup (needs n[0], n[1]
+ *               multiples of 16); 1 = 8x8 tiles, four per workgroup;
+ *   zchunk: z planes per work item (0 = the whole block; 3D only).
+ * Per batch, grid = workgroups per stage launch (0 = one per work item; else a
+ * persistent grid of that many workgroups looping over the work list).
+ * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_grid
+ * rebuild or relaunch accordingly (EINVAL for a tile the class cannot use, or
+ * a negative value).  hydro_batch_autotune times every candidate tiling of
+ * every class present (stage-1 launches on the class's own blocks; they write
+ * only the mesh's scratch stage buffer, never the arena), rejects a candidate
+ * whose stage-1 result differs from the default tiling's by more than 1e-13
+ * relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the fastest, then
+ * picks the grid the same way.  reps = timed launches per candidate (>= 1).
+ * Synchronising.  hydro_batch_get_config writes grid to out[0] and then
+ * (edge, tile, zchunk, ncells_in_class_low32) for each class, up to
+ * nclass_max classes; *nclass receives the number of classes. */
+hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk);
+hydro_status hydro_batch_set_grid(hydro_batch *b, int32_t grid);
+hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps);
+hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass);
+
+/* Kernel timing of the batched path (for roofline measurement): runs nsteps
+ * steps like hydro_batch_run but launches the two stage kernels eagerly (no
+ * graph) on the mesh stream with HIP events around each launch, and returns
+ * the mean duration in milliseconds of the stage-1 and stage-2 launches in
+ * ms_out[0] and ms_out[1], and the summed wall time of all launches of the
+ * step (stage 1 + stage 2 + finalize) per step in ms_out[2].  Same results in
+ * the arena as hydro_batch_run.  Synchronising.
+ * Errors: as hydro_batch_run. */
+hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *ms_out);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *hydro_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYDRO_H */

@@ -1,0 +1,857 @@
+// api.hip -- host side of the C ABI declared in include/hydro.h.
+//
+// Owns descriptor validation (entirely on the host, before any HIP call),
+// the device block table, the work lists of packets and batches, the
+// stage-synchronous plain path, the HIP-graph batched path and the autotuner.
+// Kernels live in kernels.hip.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hydro.h"
+#include "hydro_internal.h"
+
+using hyd::DevBlock;
+using hyd::DevTime;
+using hyd::StageArgs;
+using hyd::WorkItem;
+
+namespace {
+
+thread_local std::string g_err;
+
+hydro_status fail(hydro_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                                 \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess) return fail(HYDRO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+struct TileCfg {
+  int tile = -1;   // -1: default (16x16 when the extents allow it)
+  int zchunk = 0;  // 0: whole block
+};
+
+// Class of a block for tuning: its edge when the block is a square (2D) or a
+// cube (3D), else 0.
+int block_class(const hydro_block_desc &d, int ndim) {
+  if (d.n[0] != d.n[1]) return 0;
+  if (ndim == 3 && d.n[2] != d.n[0]) return 0;
+  return d.n[0];
+}
+
+}  // namespace
+
+struct hydro_mesh {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int ndim = 3;
+  int nblocks = 0;
+  double *arena = nullptr;
+  int64_t arena_len = 0;
+  double *u1 = nullptr;  // first-stage state, same layout as the arena
+  DevBlock *d_blocks = nullptr;
+  std::vector<hydro_block_desc> desc;
+  int children = 0;  // live packets and batches
+  int num_cu = 0;
+};
+
+struct WorkList {
+  WorkItem *d_items = nullptr;
+  int nitems = 0;
+  int kmask = 0;
+};
+
+struct hydro_packet {
+  hydro_mesh *m = nullptr;
+  std::vector<int32_t> ids;
+  int prec = HYDRO_FP64;
+  WorkList wl;
+  DevTime *d_time = nullptr;
+  bool closed = false;
+  bool lam_valid = false;  // the last call was an advance: d_time holds the rate of the new state
+  double lam_gamma = 0.0;
+  int batches = 0;
+};
+
+struct hydro_batch {
+  hydro_mesh *m = nullptr;
+  std::vector<hydro_packet *> packets;
+  std::vector<int32_t> ids;  // all blocks, packet order
+  int prec = HYDRO_FP64;
+  std::map<int, TileCfg> cfg;
+  int grid = 0;
+  WorkList wl;
+  DevTime *d_time = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_cfl = 0.0, g_gamma = 0.0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+hydro_status validate_mesh(const hydro_block_desc *blocks, int32_t nb, int32_t ndim, const double *arena,
+                           int64_t arena_len) {
+  if (nb <= 0 || !blocks) return fail(HYDRO_EINVAL, "mesh: nblocks must be > 0 and blocks non-null");
+  if (ndim != 2 && ndim != 3) return fail(HYDRO_EINVAL, "mesh: ndim must be 2 or 3");
+  if (!arena || arena_len <= 0) return fail(HYDRO_EINVAL, "mesh: arena must be non-null with arena_len > 0");
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  ranges.reserve(nb);
+  for (int b = 0; b < nb; ++b) {
+    const hydro_block_desc &d = blocks[b];
+    const std::string who = "mesh: block " + std::to_string(b) + ": ";
+    if (d.reserved != 0) return fail(HYDRO_EINVAL, who + "reserved field must be 0");
+    if (d.n[0] < 8 || d.n[1] < 8 || d.n[0] % 8 || d.n[1] % 8)
+      return fail(HYDRO_EINVAL, who + "n[0] and n[1] must be positive multiples of 8");
+    if (d.n[0] > 16384 || d.n[1] > 16384) return fail(HYDRO_EINVAL, who + "n[0], n[1] must be <= 16384");
+    if (ndim == 2 && d.n[2] != 1) return fail(HYDRO_EINVAL, who + "n[2] must be 1 in 2D");
+    if (ndim == 3 && (d.n[2] < 2 || d.n[2] > 16384)) return fail(HYDRO_EINVAL, who + "n[2] must be in [2, 16384] in 3D");
+    const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    if (nc >= ((int64_t)1 << 31)) return fail(HYDRO_EINVAL, who + "too many cells");
+    for (int a = 0; a < ndim; ++a)
+      if (!finite_pos(d.dx[a])) return fail(HYDRO_EINVAL, who + "dx must be finite and > 0");
+    if (d.offset < 0 || d.offset > arena_len - 5 * nc) return fail(HYDRO_EINVAL, who + "range outside the arena");
+    ranges.emplace_back(d.offset, d.offset + 5 * nc);
+    for (int f = 0; f < 2 * ndim; ++f) {
+      const int k = d.face_kind[f];
+      if (k != HYDRO_NBR && k != HYDRO_OUTFLOW && k != HYDRO_PERIODIC_SELF)
+        return fail(HYDRO_EINVAL, who + "bad face kind on face " + std::to_string(f));
+      if (k != HYDRO_NBR) continue;
+      const int s = d.nbr[f];
+      if (s < 0 || s >= nb) return fail(HYDRO_EINVAL, who + "neighbour id out of range on face " + std::to_string(f));
+      const int axis = f / 2;
+      for (int a = 0; a < 3; ++a)
+        if (a != axis && blocks[s].n[a] != d.n[a])
+          return fail(HYDRO_EINVAL, who + "neighbour on face " + std::to_string(f) + " has other tangential extents");
+      if (blocks[s].n[axis] < 2) return fail(HYDRO_EINVAL, who + "neighbour too thin for two guard layers");
+    }
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second) return fail(HYDRO_EINVAL, "mesh: block ranges overlap in the arena");
+  return HYDRO_OK;
+}
+
+DevBlock make_devblock(const hydro_block_desc *all, int b, int ndim) {
+  const hydro_block_desc &d = all[b];
+  DevBlock B;
+  std::memset(&B, 0, sizeof(B));
+  B.off = d.offset;
+  for (int a = 0; a < 3; ++a) {
+    B.n[a] = d.n[a];
+    B.dx[a] = (a < ndim) ? d.dx[a] : 1.0;
+  }
+  B.ncell = d.n[0] * d.n[1] * d.n[2];
+  for (int f = 0; f < 6; ++f) {
+    const int axis = f / 2;
+    int kind = (f < 2 * ndim) ? d.face_kind[f] : HYDRO_OUTFLOW;
+    const int src = (kind == HYDRO_NBR) ? d.nbr[f] : b;
+    const hydro_block_desc &s = all[src];
+    B.foff[f] = s.offset;
+    B.fnax[f] = s.n[axis];
+    B.fnc[f] = s.n[0] * s.n[1] * s.n[2];
+    B.fmode[f] = (kind == HYDRO_OUTFLOW) ? 1 : 0;
+  }
+  return B;
+}
+
+// ---------------------------------------------------------------- work lists
+// Items in block order; 8x8 tiles are packed four to an item (tiles of equal
+// z range only).
+void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
+                 std::vector<WorkItem> &items, int &kmask) {
+  items.clear();
+  kmask = 0;
+  std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> pending;
+  auto emit8 = [&](std::vector<std::array<int, 3>> &q, int z0, int z1) {
+    WorkItem it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = hyd::KIND_T8;
+    it.z0 = (int16_t)z0;
+    it.z1 = (int16_t)z1;
+    for (int s = 0; s < 4; ++s) {
+      if (s < (int)q.size()) {
+        it.block[s] = q[s][0];
+        it.x0[s] = (int16_t)q[s][1];
+        it.y0[s] = (int16_t)q[s][2];
+      } else {
+        it.block[s] = -1;
+      }
+    }
+    q.clear();
+    items.push_back(it);
+    kmask |= 2;
+  };
+  for (int32_t b : ids) {
+    const hydro_block_desc &d = m->desc[b];
+    TileCfg c;
+    auto f = cfg.find(block_class(d, m->ndim));
+    if (f != cfg.end()) c = f->second;
+    const bool can16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
+    const bool use16 = can16 && c.tile != 1;
+    const int nz = d.n[2];
+    const int zc = (m->ndim == 3) ? (c.zchunk > 0 ? std::min(c.zchunk, nz) : nz) : 1;
+    for (int z0 = 0; z0 < nz; z0 += zc) {
+      const int z1 = std::min(nz, z0 + zc);
+      const int T = use16 ? 16 : 8;
+      for (int y0 = 0; y0 < d.n[1]; y0 += T)
+        for (int x0 = 0; x0 < d.n[0]; x0 += T) {
+          if (use16) {
+            WorkItem it;
+            std::memset(&it, 0, sizeof(it));
+            it.kind = hyd::KIND_T16;
+            it.block[0] = b;
+            it.block[1] = it.block[2] = it.block[3] = -1;
+            it.x0[0] = (int16_t)x0;
+            it.y0[0] = (int16_t)y0;
+            it.z0 = (int16_t)z0;
+            it.z1 = (int16_t)z1;
+            items.push_back(it);
+            kmask |= 1;
+          } else {
+            auto &q = pending[{z0, z1}];
+            q.push_back({b, x0, y0});
+            if (q.size() == 4) emit8(q, z0, z1);
+          }
+        }
+    }
+  }
+  for (auto &kv : pending)
+    if (!kv.second.empty()) emit8(kv.second, kv.first.first, kv.first.second);
+}
+
+hydro_status upload_items(const std::vector<WorkItem> &items, int kmask, WorkList &wl, hipStream_t s) {
+  WorkItem *d = nullptr;
+  if (!items.empty()) {
+    if (hipMalloc(&d, items.size() * sizeof(WorkItem)) != hipSuccess)
+      return fail(HYDRO_ENOMEM, "work list: hipMalloc failed");
+    hipError_t e = hipMemcpyAsync(d, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(HYDRO_EDEVICE, std::string("work list upload: ") + hipGetErrorString(e));
+    }
+  }
+  if (wl.d_items) (void)hipFree(wl.d_items);
+  wl.d_items = d;
+  wl.nitems = (int)items.size();
+  wl.kmask = kmask;
+  return HYDRO_OK;
+}
+
+hydro_status alloc_time(DevTime **out, hipStream_t s) {
+  DevTime *t = nullptr;
+  if (hipMalloc(&t, sizeof(DevTime)) != hipSuccess) return fail(HYDRO_ENOMEM, "hipMalloc of time record failed");
+  DevTime h;
+  std::memset(&h, 0, sizeof(h));
+  h.bad_block = INT_MAX;
+  hipError_t e = hipMemcpyAsync(t, &h, sizeof(h), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(t);
+    return fail(HYDRO_EDEVICE, std::string("time record init: ") + hipGetErrorString(e));
+  }
+  *out = t;
+  return HYDRO_OK;
+}
+
+StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double dt, const DevTime *dt_dev,
+                     DevTime *acc, double gamma, int reset) {
+  StageArgs a;
+  a.blocks = m->d_blocks;
+  a.items = wl.d_items;
+  a.nitems = wl.nitems;
+  a.reset_time = reset;
+  a.src = (stage == 1) ? m->arena : m->u1;
+  a.un = m->arena;
+  a.dst = (stage == 1) ? m->u1 : m->arena;
+  a.dt = dt;
+  a.dt_dev = dt_dev;
+  a.acc = acc;
+  a.gamma = gamma;
+  return a;
+}
+
+int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
+
+hydro_status launch_stage_wl(const hydro_mesh *m, bool mixed, int stage, const WorkList &wl, int grid,
+                             hipStream_t s, const StageArgs &a) {
+  hipError_t e = hyd::launch_stage(m->ndim, mixed, stage, wl.kmask, grid_of(wl, grid), s, a);
+  if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
+  return HYDRO_OK;
+}
+
+hydro_status read_time(const hydro_mesh *m, const DevTime *d, DevTime &h) {
+  HIP_TRY(hipMemcpyAsync(&h, d, sizeof(DevTime), hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(hipStreamSynchronize(m->stream));
+  return HYDRO_OK;
+}
+
+hydro_status nonphys(const DevTime &h) {
+  return fail(HYDRO_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite)" +
+                                  (h.bad_block != INT_MAX ? " in block " + std::to_string(h.bad_block) : std::string()));
+}
+
+hydro_status rebuild_batch_items(hydro_batch *b) {
+  std::vector<WorkItem> items;
+  int kmask = 0;
+  build_items(b->m, b->ids, b->cfg, items, kmask);
+  hydro_status st = upload_items(items, kmask, b->wl, b->m->stream);
+  if (st) return st;
+  // the captured graph holds the old work list
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  return HYDRO_OK;
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *hydro_last_error(void) { return g_err.c_str(); }
+
+hydro_status hydro_mesh_create(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *arena,
+                               int64_t arena_len, void *stream, hydro_mesh **out) {
+  if (!out) return fail(HYDRO_EINVAL, "mesh: out is null");
+  *out = nullptr;
+  hydro_status st = validate_mesh(blocks, nblocks, ndim, arena, arena_len);
+  if (st) return st;
+
+  hydro_mesh *m = new hydro_mesh();
+  m->ndim = ndim;
+  m->nblocks = nblocks;
+  m->arena = arena;
+  m->arena_len = arena_len;
+  m->stream = (hipStream_t)stream;
+  m->desc.assign(blocks, blocks + nblocks);
+  std::vector<DevBlock> hb(nblocks);
+  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(blocks, b, ndim);
+
+  auto cleanup = [&](hydro_status s, const std::string &msg) {
+    if (m->u1) (void)hipFree(m->u1);
+    if (m->d_blocks) (void)hipFree(m->d_blocks);
+    delete m;
+    return fail(s, msg);
+  };
+  if (hipGetDevice(&m->device) != hipSuccess) return cleanup(HYDRO_EDEVICE, "mesh: no HIP device");
+  if (hipDeviceGetAttribute(&m->num_cu, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess)
+    return cleanup(HYDRO_EDEVICE, "mesh: device query failed");
+  if (hipMalloc(&m->u1, (size_t)arena_len * sizeof(double)) != hipSuccess)
+    return cleanup(HYDRO_ENOMEM, "mesh: hipMalloc of the stage buffer failed");
+  if (hipMalloc(&m->d_blocks, (size_t)nblocks * sizeof(DevBlock)) != hipSuccess)
+    return cleanup(HYDRO_ENOMEM, "mesh: hipMalloc of the block table failed");
+  hipError_t e = hipMemcpyAsync(m->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) return cleanup(HYDRO_EDEVICE, std::string("mesh: block table upload: ") + hipGetErrorString(e));
+  *out = m;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_mesh_destroy(hydro_mesh *m) {
+  if (!m) return fail(HYDRO_EINVAL, "mesh is null");
+  if (m->children) return fail(HYDRO_ESTATE, "mesh still has packets or batches");
+  (void)hipStreamSynchronize(m->stream);
+  (void)hipFree(m->u1);
+  (void)hipFree(m->d_blocks);
+  delete m;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_packet_create(hydro_mesh *m, const int32_t *block_ids, int32_t nblocks, int32_t precision,
+                                 hydro_packet **out) {
+  if (!out) return fail(HYDRO_EINVAL, "packet: out is null");
+  *out = nullptr;
+  if (!m) return fail(HYDRO_EINVAL, "packet: mesh is null");
+  if (!block_ids || nblocks <= 0) return fail(HYDRO_EINVAL, "packet: need at least one block id");
+  if (precision != HYDRO_FP64 && precision != HYDRO_FP32_FP64) return fail(HYDRO_EINVAL, "packet: bad precision");
+  std::vector<char> seen(m->nblocks, 0);
+  for (int i = 0; i < nblocks; ++i) {
+    const int b = block_ids[i];
+    if (b < 0 || b >= m->nblocks) return fail(HYDRO_EINVAL, "packet: block id out of range");
+    if (seen[b]) return fail(HYDRO_EINVAL, "packet: duplicate block id " + std::to_string(b));
+    seen[b] = 1;
+  }
+  hydro_packet *p = new hydro_packet();
+  p->m = m;
+  p->ids.assign(block_ids, block_ids + nblocks);
+  p->prec = precision;
+  p->closed = true;
+  for (int b : p->ids)
+    for (int f = 0; f < 2 * m->ndim; ++f)
+      if (m->desc[b].face_kind[f] == HYDRO_NBR && !seen[m->desc[b].nbr[f]]) p->closed = false;
+  std::vector<WorkItem> items;
+  int kmask = 0;
+  build_items(m, p->ids, {}, items, kmask);
+  hydro_status st = upload_items(items, kmask, p->wl, m->stream);
+  if (!st) st = alloc_time(&p->d_time, m->stream);
+  if (st) {
+    if (p->wl.d_items) (void)hipFree(p->wl.d_items);
+    delete p;
+    return st;
+  }
+  m->children++;
+  *out = p;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_packet_destroy(hydro_packet *p) {
+  if (!p) return fail(HYDRO_EINVAL, "packet is null");
+  if (p->batches) return fail(HYDRO_ESTATE, "packet is still part of a batch");
+  (void)hipStreamSynchronize(p->m->stream);
+  (void)hipFree(p->wl.d_items);
+  (void)hipFree(p->d_time);
+  p->m->children--;
+  delete p;
+  return HYDRO_OK;
+}
+
+static hydro_status check_step_args(double dt, double gamma) {
+  if (!finite_pos(dt)) return fail(HYDRO_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  return HYDRO_OK;
+}
+
+hydro_status hydro_packet_advance(hydro_packet *p, double dt, double gamma) {
+  if (!p) return fail(HYDRO_EINVAL, "packet is null");
+  hydro_status st = check_step_args(dt, gamma);
+  if (st) return st;
+  if (!p->closed)
+    return fail(HYDRO_ESTATE, "packet is not closed under its NBR links; use a batch to keep stages synchronous");
+  hydro_mesh *m = p->m;
+  const bool mixed = p->prec == HYDRO_FP32_FP64;
+  p->lam_valid = false;
+  st = launch_stage_wl(m, mixed, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
+  if (st) return st;
+  st = launch_stage_wl(m, mixed, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
+  if (st) return st;
+  p->lam_valid = true;
+  p->lam_gamma = gamma;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, double *dt_out) {
+  if (!p || !dt_out) return fail(HYDRO_EINVAL, "packet and dt_out must be non-null");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  hydro_mesh *m = p->m;
+  if (!(p->lam_valid && p->lam_gamma == gamma)) {
+    hipError_t e = hyd::launch_reset(p->d_time, m->stream);
+    if (e == hipSuccess)
+      e = hyd::launch_lambda(m->ndim, p->wl.kmask, p->wl.nitems, m->stream,
+                             stage_args(m, p->wl, 1, 0.0, nullptr, p->d_time, gamma, 0));
+    if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("rate launch: ") + hipGetErrorString(e));
+  }
+  DevTime h;
+  hydro_status st = read_time(m, p->d_time, h);
+  if (st) return st;
+  if (h.status) return nonphys(h);
+  const double lam = [&] {
+    double d;
+    std::memcpy(&d, &h.lam_bits, sizeof(d));
+    return d;
+  }();
+  if (!(lam > 0.0)) return fail(HYDRO_ENONPHYS, "CFL rate is zero or invalid");
+  *dt_out = cfl / lam;
+  p->lam_valid = true;
+  p->lam_gamma = gamma;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, hydro_batch **out) {
+  if (!out) return fail(HYDRO_EINVAL, "batch: out is null");
+  *out = nullptr;
+  if (!packets || npackets <= 0) return fail(HYDRO_EINVAL, "batch: need at least one packet");
+  hydro_mesh *m = packets[0] ? packets[0]->m : nullptr;
+  if (!m) return fail(HYDRO_EINVAL, "batch: null packet");
+  const int prec = packets[0]->prec;
+  std::vector<char> seen(m->nblocks, 0);
+  std::vector<int32_t> ids;
+  for (int i = 0; i < npackets; ++i) {
+    const hydro_packet *p = packets[i];
+    if (!p || p->m != m) return fail(HYDRO_EINVAL, "batch: packets must share one mesh");
+    if (p->prec != prec) return fail(HYDRO_EINVAL, "batch: packets must share one precision");
+    for (int b : p->ids) {
+      if (seen[b]) return fail(HYDRO_EINVAL, "batch: block " + std::to_string(b) + " is in two packets");
+      seen[b] = 1;
+      ids.push_back(b);
+    }
+  }
+  hydro_batch *bt = new hydro_batch();
+  bt->m = m;
+  bt->packets.assign(packets, packets + npackets);
+  bt->ids = std::move(ids);
+  bt->prec = prec;
+  hydro_status st = rebuild_batch_items(bt);
+  if (!st) st = alloc_time(&bt->d_time, m->stream);
+  if (!st && hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    st = fail(HYDRO_EDEVICE, "batch: stream creation failed");
+  if (st) {
+    if (bt->wl.d_items) (void)hipFree(bt->wl.d_items);
+    if (bt->d_time) (void)hipFree(bt->d_time);
+    delete bt;
+    return st;
+  }
+  for (auto *p : bt->packets) p->batches++;
+  m->children++;
+  *out = bt;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_destroy(hydro_batch *b) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  (void)hipStreamSynchronize(b->m->stream);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  (void)hipFree(b->wl.d_items);
+  (void)hipFree(b->d_time);
+  for (auto *p : b->packets) p->batches--;
+  b->m->children--;
+  delete b;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_advance_plain(hydro_batch *b, double dt, double gamma) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  hydro_status st = check_step_args(dt, gamma);
+  if (st) return st;
+  hydro_mesh *m = b->m;
+  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  for (auto *p : b->packets) {
+    p->lam_valid = false;
+    st = launch_stage_wl(m, mixed, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
+    if (st) return st;
+  }
+  for (auto *p : b->packets) {
+    st = launch_stage_wl(m, mixed, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
+    if (st) return st;
+    p->lam_valid = true;
+    p->lam_gamma = gamma;
+  }
+  return HYDRO_OK;
+}
+
+static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
+  hydro_mesh *m = b->m;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hydro_status st =
+      launch_stage_wl(m, mixed, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0));
+  if (!st)
+    st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, b->cap_stream,
+                         stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0));
+  if (!st && hyd::launch_finalize(b->d_time, cfl, 0, b->cap_stream) != hipSuccess)
+    st = fail(HYDRO_EDEVICE, "finalize launch failed");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(HYDRO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  b->graph = g;
+  b->g_cfl = cfl;
+  b->g_gamma = gamma;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  hydro_mesh *m = b->m;
+  if (!b->gexec || b->g_cfl != cfl || b->g_gamma != gamma) {
+    hydro_status st = capture_step(b, cfl, gamma);
+    if (st) return st;
+  }
+  for (auto *p : b->packets) p->lam_valid = false;
+  // dt of the first step from the current state
+  hipError_t e = hyd::launch_reset(b->d_time, m->stream);
+  if (e == hipSuccess)
+    e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
+                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0));
+  if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
+  if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
+  for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(b->gexec, m->stream));
+  DevTime h;
+  hydro_status st = read_time(m, b->d_time, h);
+  if (st) return st;
+  if (h.status) return nonphys(h);
+  if (t_out) *t_out = h.t;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *ms_out) {
+  if (!b || !ms_out) return fail(HYDRO_EINVAL, "batch and ms_out must be non-null");
+  if (nsteps < 1) return fail(HYDRO_EINVAL, "nsteps must be >= 1");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  hydro_mesh *m = b->m;
+  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  for (auto *p : b->packets) p->lam_valid = false;
+  hipError_t e = hyd::launch_reset(b->d_time, m->stream);
+  if (e == hipSuccess)
+    e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
+                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0));
+  if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
+  if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
+  std::vector<hipEvent_t> ev(3 * nsteps + 1, nullptr);
+  for (auto &x : ev) HIP_TRY(hipEventCreate(&x));
+  hydro_status st = HYDRO_OK;
+  HIP_TRY(hipEventRecord(ev[0], m->stream));
+  for (int s = 0; s < nsteps && !st; ++s) {
+    st = launch_stage_wl(m, mixed, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0));
+    if (!st && hipEventRecord(ev[3 * s + 1], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
+    if (!st)
+      st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0));
+    if (!st && hipEventRecord(ev[3 * s + 2], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
+    if (!st && hyd::launch_finalize(b->d_time, cfl, 0, m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "finalize");
+    if (!st && hipEventRecord(ev[3 * s + 3], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
+  }
+  if (!st && hipEventSynchronize(ev[3 * nsteps]) != hipSuccess) st = fail(HYDRO_EDEVICE, "event sync");
+  double t1 = 0, t2 = 0, tall = 0;
+  for (int s = 0; s < nsteps && !st; ++s) {
+    float a = 0, c = 0, d = 0;
+    (void)hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]);
+    (void)hipEventElapsedTime(&c, ev[3 * s + 1], ev[3 * s + 2]);
+    (void)hipEventElapsedTime(&d, ev[3 * s], ev[3 * s + 3]);
+    t1 += a;
+    t2 += c;
+    tall += d;
+  }
+  for (auto &x : ev) (void)hipEventDestroy(x);
+  if (st) return st;
+  DevTime h;
+  st = read_time(m, b->d_time, h);
+  if (st) return st;
+  if (h.status) return nonphys(h);
+  ms_out[0] = t1 / nsteps;
+  ms_out[1] = t2 / nsteps;
+  ms_out[2] = tall / nsteps;
+  return HYDRO_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  if (tile != 0 && tile != 1) return fail(HYDRO_EINVAL, "tile must be 0 (16x16) or 1 (8x8)");
+  if (zchunk < 0) return fail(HYDRO_EINVAL, "zchunk must be >= 0");
+  if (tile == 0 && edge > 0 && edge % 16) return fail(HYDRO_EINVAL, "16x16 tiles need an edge multiple of 16");
+  TileCfg c;
+  c.tile = tile;
+  c.zchunk = zchunk;
+  b->cfg[edge] = c;
+  return rebuild_batch_items(b);
+}
+
+hydro_status hydro_batch_set_grid(hydro_batch *b, int32_t grid) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  if (grid < 0) return fail(HYDRO_EINVAL, "grid must be >= 0");
+  if (grid != b->grid) {
+    b->grid = grid;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+  }
+  return HYDRO_OK;
+}
+
+hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass) {
+  if (!b || !out || !nclass || nclass_max < 0) return fail(HYDRO_EINVAL, "bad arguments");
+  std::map<int, int64_t> cells;
+  for (int id : b->ids) {
+    const hydro_block_desc &d = b->m->desc[id];
+    cells[block_class(d, b->m->ndim)] += (int64_t)d.n[0] * d.n[1] * d.n[2];
+  }
+  out[0] = b->grid;
+  int k = 0;
+  for (auto &kv : cells) {
+    if (k < nclass_max) {
+      TileCfg c;
+      auto f = b->cfg.find(kv.first);
+      if (f != b->cfg.end()) c = f->second;
+      const hydro_block_desc *any = nullptr;
+      for (int id : b->ids)
+        if (block_class(b->m->desc[id], b->m->ndim) == kv.first) {
+          any = &b->m->desc[id];
+          break;
+        }
+      const bool can16 = any && any->n[0] % 16 == 0 && any->n[1] % 16 == 0;
+      out[1 + 4 * k + 0] = kv.first;
+      out[1 + 4 * k + 1] = (can16 && c.tile != 1) ? 0 : 1;
+      out[1 + 4 * k + 2] = c.zchunk;
+      out[1 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
+    }
+    ++k;
+  }
+  *nclass = k;
+  return HYDRO_OK;
+}
+
+// Median time of `reps` stage-1 launches of a work list (ms).
+static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, double gamma, int reps, double &ms) {
+  hydro_mesh *m = b->m;
+  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<double> t;
+  hydro_status st = HYDRO_OK;
+  const double dt = 1e-30;  // the result is scratch; any positive dt
+  StageArgs a = stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0);
+  st = launch_stage_wl(m, mixed, 1, wl, grid, m->stream, a);  // warm-up
+  for (int r = 0; r < reps && !st; ++r) {
+    (void)hipEventRecord(e0, m->stream);
+    st = launch_stage_wl(m, mixed, 1, wl, grid, m->stream, a);
+    (void)hipEventRecord(e1, m->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
+    float f = 0;
+    (void)hipEventElapsedTime(&f, e0, e1);
+    t.push_back(f);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  std::sort(t.begin(), t.end());
+  ms = t[t.size() / 2];
+  return HYDRO_OK;
+}
+
+static hydro_status stage1_sample(hydro_batch *b, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
+                                  double gamma, std::vector<double> &out) {
+  hydro_mesh *m = b->m;
+  std::vector<WorkItem> items;
+  int kmask;
+  WorkList wl;
+  build_items(m, ids, cfg, items, kmask);
+  hydro_status st = upload_items(items, kmask, wl, m->stream);
+  if (st) return st;
+  st = launch_stage_wl(m, b->prec == HYDRO_FP32_FP64, 1, wl, 0, m->stream,
+                       stage_args(m, wl, 1, 1e-3, nullptr, b->d_time, gamma, 0));
+  out.clear();
+  for (int id : ids) {
+    if (st) break;
+    const hydro_block_desc &d = m->desc[id];
+    const size_t len = (size_t)5 * d.n[0] * d.n[1] * d.n[2];
+    const size_t o = out.size();
+    out.resize(o + len);
+    if (hipMemcpyAsync(out.data() + o, m->u1 + d.offset, len * sizeof(double), hipMemcpyDeviceToHost, m->stream) !=
+        hipSuccess)
+      st = fail(HYDRO_EDEVICE, "tuning: readback failed");
+  }
+  if (!st && hipStreamSynchronize(m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: sync failed");
+  (void)hipFree(wl.d_items);
+  return st;
+}
+
+hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  if (reps < 1) return fail(HYDRO_EINVAL, "reps must be >= 1");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  hydro_mesh *m = b->m;
+  const double tol = (b->prec == HYDRO_FP32_FP64) ? 1e-6 : 1e-13;
+  std::map<int, std::vector<int32_t>> cls;
+  for (int id : b->ids) cls[block_class(m->desc[id], m->ndim)].push_back(id);
+  for (auto &kv : cls) {
+    const int edge = kv.first;
+    const std::vector<int32_t> &ids = kv.second;
+    const hydro_block_desc &d0 = m->desc[ids[0]];
+    bool can16 = true;
+    for (int id : ids) can16 = can16 && m->desc[id].n[0] % 16 == 0 && m->desc[id].n[1] % 16 == 0;
+    std::vector<TileCfg> cands;
+    std::vector<int> zcs = {0};
+    if (m->ndim == 3)
+      for (int zc : {d0.n[2] / 2, d0.n[2] / 4})
+        if (zc >= 4) zcs.push_back(zc);
+    for (int tile : {0, 1}) {
+      if (tile == 0 && !can16) continue;
+      for (int zc : zcs) {
+        TileCfg c;
+        c.tile = tile;
+        c.zchunk = zc;
+        cands.push_back(c);
+      }
+    }
+    // parity reference: default tiling on a sample of blocks
+    std::vector<int32_t> sample(ids.begin(), ids.begin() + std::min<size_t>(ids.size(), 64));
+    std::vector<double> ref, got;
+    hydro_status st = stage1_sample(b, sample, {}, gamma, ref);
+    if (st) return st;
+    double best = 1e300;
+    TileCfg bestc;
+    for (const TileCfg &c : cands) {
+      std::map<int, TileCfg> one;
+      one[edge] = c;
+      st = stage1_sample(b, sample, one, gamma, got);
+      if (st) return st;
+      bool ok = got.size() == ref.size();
+      double scale = 0.0;
+      for (double r : ref) scale = std::max(scale, std::fabs(r));
+      for (size_t i = 0; ok && i < ref.size(); ++i)
+        ok = std::fabs(got[i] - ref[i]) <= tol * (std::fabs(ref[i]) + 1e-6 * scale);
+      if (!ok) continue;
+      std::vector<WorkItem> items;
+      int kmask;
+      WorkList wl;
+      build_items(m, ids, one, items, kmask);
+      st = upload_items(items, kmask, wl, m->stream);
+      if (st) return st;
+      double ms = 0;
+      st = time_stage1(b, wl, 0, gamma, reps, ms);
+      (void)hipFree(wl.d_items);
+      if (st) return st;
+      if (ms < best) {
+        best = ms;
+        bestc = c;
+      }
+    }
+    b->cfg[edge] = bestc;
+  }
+  hydro_status st = rebuild_batch_items(b);
+  if (st) return st;
+  // grid: one workgroup per item, or persistent grids of k workgroups per CU
+  double best = 1e300;
+  int bestg = 0;
+  for (int g : {0, 2 * m->num_cu, 4 * m->num_cu, 8 * m->num_cu}) {
+    if (g > 0 && g >= b->wl.nitems) continue;
+    double ms = 0;
+    st = time_stage1(b, b->wl, g, gamma, reps, ms);
+    if (st) return st;
+    if (ms < best) {
+      best = ms;
+      bestg = g;
+    }
+  }
+  return hydro_batch_set_grid(b, bestg);
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal types shared by the HIP kernels (kernels.hip) and the host library
+// (api.hip).  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hyd {
+
+constexpr int NVAR = 5;
+constexpr int WG = 256;  // threads per workgroup of every stage kernel
+
+// Device copy of one block, with the guard sources of its six faces resolved.
+// Face f (-x,+x,-y,+y,-z,+z) copies its two guard layers from block
+// data at element offset foff[f]: that block's extent along the face axis is
+// fnax[f], its cell count fnc[f].  fmode[f] = 0: wrap (the far layers of the
+// source, which is a linked neighbour or the block itself); 1: outflow (the
+// edge layer of the block itself, repeated).
+struct DevBlock {
+  int64_t off;
+  int32_t n[3];
+  int32_t ncell;
+  double dx[3];
+  int64_t foff[6];
+  int32_t fnax[6];
+  int32_t fnc[6];
+  int32_t fmode[6];
+  int32_t pad[2];
+};
+
+// One work item of a stage launch: a column of x-y tiles marched over
+// z planes [z0, z1).  kind 0: one 16x16 tile (block[0]); kind 1: up to four
+// 8x8 tiles, one per 64-thread wave, from any blocks (block[s] < 0 = empty).
+struct WorkItem {
+  int32_t block[4];
+  int16_t x0[4];
+  int16_t y0[4];
+  int16_t z0, z1;
+  int32_t kind;
+};
+
+enum { KIND_T16 = 0, KIND_T8 = 1 };
+
+// Device-resident step bookkeeping of a packet or batch.
+struct DevTime {
+  double dt;                    // time step used by the next stage launches (graph path)
+  double t;                     // simulated time advanced by the graph path
+  unsigned long long lam_bits;  // max CFL rate as the bits of a non-negative double
+  int32_t status;               // nonzero: a non-physical state was seen
+  int32_t bad_block;            // smallest block id with a non-physical state
+  uint32_t wq_next;             // dynamic work queue: next item
+  uint32_t wq_done;             // dynamic work queue: workgroups finished
+};
+
+struct StageArgs {
+  const DevBlock *blocks;
+  const WorkItem *items;
+  int32_t nitems;
+  int32_t reset_time;  // 1: workgroup 0 clears lam/status of `acc` first (plain path)
+  const double *src;   // state the fluxes are computed from (Un or U1)
+  const double *un;    // Un (stage 2 only)
+  double *dst;         // U1 (stage 1) or Un+1 (stage 2, may alias un)
+  double dt;           // used when dt_dev is null
+  const DevTime *dt_dev;
+  DevTime *acc;        // CFL rate and status accumulator
+  double gamma;
+};
+
+// kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int grid, hipStream_t s, const StageArgs &a);
+hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a);
+hipError_t launch_reset(DevTime *t, hipStream_t s);
+hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s);
+
+}  // namespace hyd

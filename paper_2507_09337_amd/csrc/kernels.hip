@@ -1,0 +1,599 @@
+// kernels.hip -- HIP kernels (gfx950) of one explicit finite-volume
+// compressible-Euler SSP-RK2 stage over a list of work items.
+//
+// Method (arXiv 2507.09337, Sec. 6: explicit finite volume with a guard-cell
+// halo, 2nd-order Runge-Kutta refreshing guards before each stage; Sec. 5.2:
+// ideal-gas gamma-law EOS).  Reconstruction and flux follow the textbook
+// methods named in include/hydro.h: PLM on primitives with minmod, HLLC with
+// Davis wave speeds, SSP-RK2 combine, CFL rate sum_d (|u_d| + c)/dx_d.
+//
+// Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
+//   * One workgroup = 256 threads = one x-y tile of a block (16x16) or four
+//     independent 8x8 tiles (one per wave).  The workgroup marches its tile
+//     column through the z planes of the block ("2.5-D"): the z direction
+//     lives in registers (a four-plane sliding window of primitives per
+//     thread, so every z face is computed once by the thread below it), the
+//     current plane with its x/y guard ring lives in LDS.
+//   * Guard cells are never stored: a tile load gathers them from the linked
+//     neighbour block's interior (or wraps / repeats the edge), so HBM holds
+//     interior cells only and there is no guard-fill pass.
+//   * Loads are struct-of-arrays, one variable per instruction, x-fastest, so
+//     a wave reads whole 128-byte lines.
+//   * Every x and y face of a plane is one "face job" computed once from LDS
+//     and shared by its two cells; the update differences the shared fluxes,
+//     so the flux sum telescopes and mass, momentum and energy are conserved
+//     to the rounding of the FP64 update.
+//   * Primitive recovery (with e = E - rho|v|^2/2, where cancellation
+//     happens), the RK combine and the CFL rate are always FP64.  In the mixed
+//     variant the recovered primitives are rounded to FP32, reconstruction and
+//     HLLC run in FP32 (hardware rcp/rsqrt), and the FP32 face fluxes are
+//     widened to FP64 before they are differenced.
+//   * The CFL rate of the new state is reduced in the stage-2 epilogue:
+//     wave64 shuffles, then one 64-bit atomic max per wave on the bit pattern
+//     of a non-negative double.  No MFMA: this is a stencil, not a contraction.
+#include <climits>
+#include <type_traits>
+
+#include "hydro_internal.h"
+
+namespace hyd {
+
+// ------------------------------------------------------------------------
+// Arithmetic of the two precisions.
+// ------------------------------------------------------------------------
+template <typename T>
+struct Arith;
+
+template <>
+struct Arith<double> {  // IEEE division and square root
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double sound(double g, double p, double r) { return __builtin_sqrt(g * p / r); }
+};
+
+template <>
+struct Arith<float> {  // hardware reciprocal and reciprocal square root (about 1 ulp)
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  // c = sqrt(g p / r) = g p / sqrt(g p r)
+  static __device__ __forceinline__ float sound(float g, float p, float r) {
+    float gp = g * p;
+    return gp * __builtin_amdgcn_rsqf(gp * r);
+  }
+};
+
+// minmod: the smaller-magnitude argument when both have the same strict sign, else 0.
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  T pos = (a < b) ? a : b;
+  T neg = (a > b) ? a : b;
+  return (a > T(0) && b > T(0)) ? pos : ((a < T(0) && b < T(0)) ? neg : T(0));
+}
+
+// PLM face states between w1 and w2 of four consecutive cells.
+template <typename T>
+__device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
+  T d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
+  l = w1 + T(0.5) * minmod(d01, d12);
+  r = w2 - T(0.5) * minmod(d12, d23);
+}
+
+// HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).
+// The side of the contact is chosen first (left if S_L >= 0 or S* >= 0) and
+// only that side's physical flux and star state are formed:
+//   F = F_K + S (U*_K - U_K),  S = min(S_L, 0) on the left, max(S_R, 0) on the
+// right, which reproduces the four textbook branches (S = 0 gives F_K).
+// The star state is written with one reciprocal of (S_K - S*):
+//   q = (S_K - u)/(S_K - S*), rho* = rho q,
+//   E* = q E + rho* (S* - u) S* + (S* - u) p /(S_K - S*).
+template <typename T>
+__device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T F[5]) {
+  using A = Arith<T>;
+  const T cL = A::sound(g, L[4], L[0]);
+  const T cR = A::sound(g, R[4], R[0]);
+  const T SL = fmin(L[1] - cL, R[1] - cR);
+  const T SR = fmax(L[1] + cL, R[1] + cR);
+  const T aL = L[0] * (SL - L[1]);
+  const T aR = R[0] * (SR - R[1]);
+  const T Ss = A::div(R[4] - L[4] + aL * L[1] - aR * R[1], aL - aR);
+  const bool useL = (SL >= T(0)) || (Ss >= T(0));
+  const T r = useL ? L[0] : R[0];
+  const T u = useL ? L[1] : R[1];
+  const T v = useL ? L[2] : R[2];
+  const T w = useL ? L[3] : R[3];
+  const T p = useL ? L[4] : R[4];
+  const T SK = useL ? SL : SR;
+  const T S = useL ? fmin(SL, T(0)) : fmax(SR, T(0));
+  const T ru = r * u;
+  const T E = p * rgm1 + T(0.5) * r * (u * u + v * v + w * w);
+  const T f0 = ru, f1 = ru * u + p, f2 = ru * v, f3 = ru * w, f4 = u * (E + p);
+  const T inv = A::rcp(SK - Ss);
+  const T q = (SK - u) * inv;
+  const T a = r * q;
+  const T su = Ss - u;
+  const T Es = q * E + a * su * Ss + su * p * inv;
+  const bool star = (S != T(0));
+  F[0] = star ? f0 + S * (a - r) : f0;
+  F[1] = star ? f1 + S * (a * Ss - ru) : f1;
+  F[2] = star ? f2 + S * (v * (a - r)) : f2;
+  F[3] = star ? f3 + S * (w * (a - r)) : f3;
+  F[4] = star ? f4 + S * (Es - E) : f4;
+}
+
+// FP64 primitive recovery (ideal gas).  Returns false for rho <= 0, p <= 0
+// or non-finite values.
+__device__ __forceinline__ bool recover(double U0, double U1, double U2, double U3, double U4, double gm1,
+                                        double W[5]) {
+  const double inv = 1.0 / U0;
+  const double u = U1 * inv, v = U2 * inv, w = U3 * inv;
+  const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
+  const double p = gm1 * rhoe;
+  W[0] = U0;
+  W[1] = u;
+  W[2] = v;
+  W[3] = w;
+  W[4] = p;
+  const double s = fabs(u) + fabs(v) + fabs(w) + p + U0;
+  return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
+}
+
+__device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t vs, double gm1, double W[5]) {
+  return recover(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
+}
+
+// Source of an out-of-block cell along one axis: face f's source block and
+// the coordinate along the axis inside it.  `c` is -2, -1 (low face) or
+// n, n+1 (high face).
+__device__ __forceinline__ int guard_coord(const DevBlock *__restrict__ B, int f, int c, int n) {
+  const bool high = f & 1;
+  if (B->fmode[f]) return high ? n - 1 : 0;    // outflow: edge layer repeated
+  return high ? c - n : B->fnax[f] + c;        // wrap: far layers of the source
+}
+
+// Element offset of variable 0 and variable stride of cell (x, y, z) of block
+// B, at most one coordinate outside the block.
+__device__ __forceinline__ void cell_addr(const DevBlock *__restrict__ B, int x, int y, int z, int64_t &off,
+                                          int64_t &vs) {
+  const int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+  if (x < 0 || x >= nx) {
+    const int f = x < 0 ? 0 : 1;
+    const int xs = guard_coord(B, f, x, nx);
+    const int nax = B->fmode[f] ? nx : B->fnax[f];
+    off = B->foff[f] + ((int64_t)z * ny + y) * nax + xs;
+    vs = B->fmode[f] ? B->ncell : B->fnc[f];
+  } else if (y < 0 || y >= ny) {
+    const int f = y < 0 ? 2 : 3;
+    const int ys = guard_coord(B, f, y, ny);
+    const int nay = B->fmode[f] ? ny : B->fnax[f];
+    off = B->foff[f] + ((int64_t)z * nay + ys) * nx + x;
+    vs = B->fmode[f] ? B->ncell : B->fnc[f];
+  } else if (z < 0 || z >= nz) {
+    const int f = z < 0 ? 4 : 5;
+    const int zs = guard_coord(B, f, z, nz);
+    off = B->foff[f] + ((int64_t)zs * ny + y) * nx + x;
+    vs = B->fmode[f] ? B->ncell : B->fnc[f];
+  } else {
+    off = B->off + ((int64_t)z * ny + y) * nx + x;
+    vs = B->ncell;
+  }
+}
+
+template <int TX, int TY>
+struct TileGeom {
+  static constexpr int NT = TX * TY;           // threads per tile
+  static constexpr int PX = TX + 4, PY = TY + 4;
+  static constexpr int PP = PX * PY;           // padded plane (corners unused)
+  static constexpr int NXF = (TX + 1) * TY;    // x faces of a plane
+  static constexpr int NYF = TX * (TY + 1);    // y faces of a plane
+  static constexpr int ELEMS = NVAR * (PP + NXF + NYF);
+};
+
+template <int TX, int TY, int NSUB, typename T>
+constexpr size_t tile_lds_bytes() {
+  return (size_t)NSUB * TileGeom<TX, TY>::ELEMS * sizeof(T);
+}
+
+// ------------------------------------------------------------------------
+// One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
+// marched over z planes [z0, z1).
+// ------------------------------------------------------------------------
+template <int TX, int TY, int NSUB, int DIM, bool MIXED, int STAGE>
+__device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
+                                         double dt, double &lam, int &bad, int &badblk) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  using G = TileGeom<TX, TY>;
+  constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NXF = G::NXF, NYF = G::NYF;
+  static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
+  static_assert(4 * (TX + TY) <= NT, "guard ring must fit the tile's threads");
+
+  const int tid = threadIdx.x;
+  // a tile is NT/64 whole waves, so `sub` is wave-uniform: make it scalar
+  const int sub = (NSUB == 1) ? 0 : __builtin_amdgcn_readfirstlane(tid / NT);
+  const int lt = tid - sub * NT;
+  const int ti = lt % TX, tj = lt / TX;
+  T *Wp = reinterpret_cast<T *>(lds) + sub * G::ELEMS;  // [5][PY][PX] primitives of the current plane
+  T *Fx = Wp + NVAR * PP;                                // [5][TY][TX+1]
+  T *Fy = Fx + NVAR * NXF;                               // [5][TY+1][TX]
+
+  // one block per tile; uniform across the tile's waves
+  const int b = __builtin_amdgcn_readfirstlane(it->block[sub]);
+  const bool active = b >= 0;
+  const DevBlock *__restrict__ Bp = A.blocks + (active ? b : 0);
+  const int x0 = active ? __builtin_amdgcn_readfirstlane(it->x0[sub]) : 0;
+  const int y0 = active ? __builtin_amdgcn_readfirstlane(it->y0[sub]) : 0;
+  const int x = x0 + ti, y = y0 + tj;
+  const int z0 = it->z0, z1 = it->z1;
+  const double gamma = A.gamma, gm1 = gamma - 1.0;
+  const T tg = (T)gamma, trgm1 = (T)(1.0 / gm1);
+
+  double dtdx = 0, dtdy = 0, dtdz = 0, dx0 = 1, dx1 = 1, dx2 = 1;
+  int nx = 1, ny = 1, nz = 1, ncell = 1;
+  int64_t plane = 1, boff = 0;
+  if (active) {
+    nx = Bp->n[0];
+    ny = Bp->n[1];
+    nz = Bp->n[2];
+    ncell = Bp->ncell;
+    boff = Bp->off;
+    plane = (int64_t)nx * ny;
+    dx0 = Bp->dx[0];
+    dx1 = Bp->dx[1];
+    dx2 = Bp->dx[2];
+    dtdx = dt / dx0;
+    dtdy = dt / dx1;
+    if (DIM == 3) dtdz = dt / dx2;
+  }
+  const int64_t cidx = (int64_t)y * nx + x;
+
+  // ---- guard ring assignment of this thread (fixed for the whole column)
+  // threads [0, 4TY): x guards (side, layer, row); [4TY, 4TY+4TX): y guards.
+  int gslot = -1;        // LDS index of the guard cell this thread fills
+  int64_t goff = 0, gvs = 0, gps = 0;  // source offset at z = 0, variable stride, z-plane stride
+  if (active && lt < 4 * (TX + TY)) {
+    int gx, gy;
+    if (lt < 4 * TY) {
+      const int side = lt / (2 * TY), r = lt % (2 * TY), layer = r / TY + 1, row = r % TY;
+      gx = side ? TX + layer - 1 : -layer;
+      gy = row;
+    } else {
+      const int l2 = lt - 4 * TY;
+      const int side = l2 / (2 * TX), r = l2 % (2 * TX), layer = r / TX + 1, col = r % TX;
+      gx = col;
+      gy = side ? TY + layer - 1 : -layer;
+    }
+    gslot = (gy + 2) * PX + (gx + 2);
+    const int X = x0 + gx, Y = y0 + gy;
+    cell_addr(Bp, X, Y, 0, goff, gvs);
+    int64_t o1, v1;
+    cell_addr(Bp, X, Y, DIM == 3 ? 1 : 0, o1, v1);
+    gps = o1 - goff;  // the source block's z-plane stride (same block for every z)
+  }
+
+  const double *__restrict__ src = A.src;
+  const int64_t own_vs = ncell;
+  const double *__restrict__ own = src + boff + cidx;
+
+  // stage the x/y guard ring and this thread's cell of plane z into LDS
+  auto stage_plane = [&](int z, const double (&Wc)[5]) {
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Wp[v * PP + (tj + 2) * PX + (ti + 2)] = (T)Wc[v];
+    }
+    if (gslot >= 0) {
+      double Wg[5];
+      if (!load_prim(src + goff + (int64_t)z * gps, gvs, gm1, Wg)) bad = 1;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Wp[v * PP + gslot] = (T)Wg[v];
+    }
+  };
+
+  // x and y faces of the plane in LDS, each computed once
+  auto plane_faces = [&]() {
+    for (int f = lt; f < NXF + NYF; f += NT) {
+      const bool isx = f < NXF;
+      const int g = isx ? f : f - NXF;
+      int base, stride;
+      T *out;
+      int ostride;
+      if (isx) {
+        const int row = g / (TX + 1), col = g % (TX + 1);
+        base = (row + 2) * PX + col;
+        stride = 1;
+        out = Fx + row * (TX + 1) + col;
+        ostride = NXF;
+      } else {
+        const int row = g / TX, col = g % TX;
+        base = row * PX + (col + 2);
+        stride = PX;
+        out = Fy + row * TX + col;
+        ostride = NYF;
+      }
+      T wl[5], wr[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const T *p = Wp + v * PP + base;
+        plm(p[0], p[stride], p[2 * stride], p[3 * stride], wl[v], wr[v]);
+      }
+      const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
+      const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
+      T Fr[5];
+      hllc<T>(Lr, Rr, tg, trgm1, Fr);
+      out[0] = Fr[0];
+      out[ostride] = isx ? Fr[1] : Fr[2];
+      out[2 * ostride] = isx ? Fr[2] : Fr[1];
+      out[3 * ostride] = Fr[3];
+      out[4 * ostride] = Fr[4];
+    }
+  };
+
+  // RK stage update of this thread's cell in plane z
+  auto update = [&](int z, const T (&fzlo)[5], const T (&fzhi)[5]) {
+    if (!active) return;
+    const int64_t c = (int64_t)z * plane;
+    double Unew[5];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      const double fxl = (double)Fx[v * NXF + tj * (TX + 1) + ti];
+      const double fxh = (double)Fx[v * NXF + tj * (TX + 1) + ti + 1];
+      const double fyl = (double)Fy[v * NYF + tj * TX + ti];
+      const double fyh = (double)Fy[v * NYF + (tj + 1) * TX + ti];
+      double dU = dtdx * (fxl - fxh) + dtdy * (fyl - fyh);
+      if (DIM == 3) dU += dtdz * ((double)fzlo[v] - (double)fzhi[v]);
+      const double s = own[v * own_vs + c];
+      if (STAGE == 1) {
+        Unew[v] = s + dU;
+      } else {
+        const double un = A.un[boff + v * own_vs + c + cidx];
+        Unew[v] = 0.5 * un + 0.5 * (s + dU);
+      }
+      A.dst[boff + v * own_vs + c + cidx] = Unew[v];
+    }
+    if (STAGE == 2) {  // CFL rate of the new state (FP64)
+      double W[5];
+      if (!recover(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
+        bad = 1;
+        badblk = min(badblk, b);
+      } else {
+        const double cs = __builtin_sqrt(gamma * W[4] / W[0]);
+        double l = (fabs(W[1]) + cs) / dx0 + (fabs(W[2]) + cs) / dx1;
+        if (DIM == 3) l += (fabs(W[3]) + cs) / dx2;
+        lam = fmax(lam, l);
+      }
+    }
+  };
+
+  if (DIM == 2) {
+    double Wc[5] = {1, 0, 0, 0, 1};
+    if (active && !load_prim(own, own_vs, gm1, Wc)) {
+      bad = 1;
+      badblk = min(badblk, b);
+    }
+    stage_plane(0, Wc);
+    __syncthreads();
+    plane_faces();
+    __syncthreads();
+    const T zero[5] = {0, 0, 0, 0, 0};
+    update(0, zero, zero);
+    return;
+  }
+
+  // ---- 3D: z march with a four-plane register window
+  // window (wa, wb, wc) = planes (j-1, j, j+1); iteration j loads wd = plane j+2
+  // and computes the z face j+1/2 at a single site for every face of the column.
+  double Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
+  auto load_z = [&](int z, double (&W)[5]) {
+    if (!active) return;
+    int64_t off, vs;
+    if (z >= 0 && z < nz) {
+      off = boff + (int64_t)z * plane + cidx;
+      vs = own_vs;
+    } else {
+      cell_addr(Bp, x, y, z, off, vs);
+    }
+    if (!load_prim(src + off, vs, gm1, W)) {
+      bad = 1;
+      badblk = min(badblk, b);
+    }
+  };
+  load_z(z0 - 2, Wa);
+  load_z(z0 - 1, Wb);
+  load_z(z0, Wc);
+  T fzlo[5] = {0, 0, 0, 0, 0};
+  for (int j = z0 - 1; j < z1; ++j) {
+    load_z(j + 2, Wd);
+    T fz[5];
+    {
+      T wl[5], wr[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) plm((T)Wa[v], (T)Wb[v], (T)Wc[v], (T)Wd[v], wl[v], wr[v]);
+      const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
+      const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
+      T Fr[5];
+      hllc<T>(Lr, Rr, tg, trgm1, Fr);
+      fz[0] = Fr[0];
+      fz[1] = Fr[3];
+      fz[2] = Fr[2];
+      fz[3] = Fr[1];
+      fz[4] = Fr[4];
+    }
+    if (j >= z0) {
+      stage_plane(j, Wb);
+      __syncthreads();
+      plane_faces();
+      __syncthreads();
+      update(j, fzlo, fz);
+    }
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      fzlo[v] = fz[v];
+      Wa[v] = Wb[v];
+      Wb[v] = Wc[v];
+      Wc[v] = Wd[v];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// Wave/workgroup reductions into the accumulator.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void flush_acc(DevTime *acc, double lam, int bad, int badblk, bool with_lam) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    lam = fmax(lam, __shfl_xor(lam, o));
+    bad |= __shfl_xor(bad, o);
+    badblk = min(badblk, __shfl_xor(badblk, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (with_lam) atomicMax(&acc->lam_bits, (unsigned long long)__double_as_longlong(lam));
+    if (bad) {
+      atomicOr(&acc->status, 1);
+      if (badblk != INT_MAX) atomicMin(&acc->bad_block, badblk);
+    }
+  }
+}
+
+template <int KMASK, bool MIXED>
+constexpr size_t stage_lds_bytes() {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  constexpr size_t a = (KMASK & 1) ? tile_lds_bytes<16, 16, 1, T>() : 0;
+  constexpr size_t b = (KMASK & 2) ? tile_lds_bytes<8, 8, 4, T>() : 0;
+  return a > b ? a : b;
+}
+
+template <int DIM, bool MIXED, int STAGE, int KMASK>
+__global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
+  if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
+    // plain path: this launch precedes the stage-2 launch that accumulates
+    A.acc->lam_bits = 0ull;
+    A.acc->status = 0;
+    A.acc->bad_block = INT_MAX;
+  }
+  const double dt = A.dt_dev ? A.dt_dev->dt : A.dt;
+  double lam = 0.0;
+  int bad = 0, badblk = INT_MAX;
+  for (int i = blockIdx.x; i < A.nitems; i += gridDim.x) {
+    const WorkItem *it = A.items + i;
+    if ((KMASK & 1) && it->kind == KIND_T16)
+      run_tile<16, 16, 1, DIM, MIXED, STAGE>(A, it, lds, dt, lam, bad, badblk);
+    else if (KMASK & 2)
+      run_tile<8, 8, 4, DIM, MIXED, STAGE>(A, it, lds, dt, lam, bad, badblk);
+    __syncthreads();  // LDS is reused by the next item
+  }
+  // Stage 1 reports nothing: a bad Un was already reported by the rate
+  // reduction that produced dt, and a bad U1 is caught when stage 2 recovers
+  // it.  (In the plain path stage 1 also clears the accumulator, so it must
+  // not race with its own reports.)
+  if (STAGE == 2) flush_acc(A.acc, lam, bad, badblk, true);
+}
+
+// CFL rate of the interior cells of the work list (FP64).
+template <int DIM, int KMASK>
+__global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
+  double lam = 0.0;
+  int bad = 0, badblk = INT_MAX;
+  const double gm1 = A.gamma - 1.0;
+  for (int i = blockIdx.x; i < A.nitems; i += gridDim.x) {
+    const WorkItem *it = A.items + i;
+    const bool t16 = (KMASK & 1) && it->kind == KIND_T16;
+    const int TX = t16 ? 16 : 8, NT = t16 ? 256 : 64;
+    const int sub = __builtin_amdgcn_readfirstlane(threadIdx.x / NT), lt = threadIdx.x % NT;
+    const int b = __builtin_amdgcn_readfirstlane(it->block[sub]);
+    if (b < 0) continue;
+    const DevBlock &B = A.blocks[b];
+    const int x = __builtin_amdgcn_readfirstlane(it->x0[sub]) + lt % TX;
+    const int y = __builtin_amdgcn_readfirstlane(it->y0[sub]) + lt / TX;
+    const int64_t plane = (int64_t)B.n[0] * B.n[1];
+    const double *p = A.src + B.off + (int64_t)y * B.n[0] + x;
+    const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
+    for (int z = za; z < zb; ++z) {
+      double W[5];
+      if (!load_prim(p + z * plane, B.ncell, gm1, W)) {
+        bad = 1;
+        badblk = min(badblk, b);
+        continue;
+      }
+      const double cs = __builtin_sqrt(A.gamma * W[4] / W[0]);
+      double l = (fabs(W[1]) + cs) / B.dx[0] + (fabs(W[2]) + cs) / B.dx[1];
+      if (DIM == 3) l += (fabs(W[3]) + cs) / B.dx[2];
+      lam = fmax(lam, l);
+    }
+  }
+  flush_acc(A.acc, lam, bad, badblk, true);
+}
+
+__global__ void k_reset(DevTime *t) {
+  t->lam_bits = 0ull;
+  t->status = 0;
+  t->bad_block = INT_MAX;
+}
+
+// After a step (init = 0): t += dt; dt = cfl / rate of the new state.
+// Before the first step (init = 1): t = 0; dt = cfl / rate.
+__global__ void k_finalize(DevTime *t, double cfl, int init) {
+  const double lam = __longlong_as_double((long long)t->lam_bits);
+  if (init)
+    t->t = 0.0;
+  else
+    t->t += t->dt;
+  t->dt = (t->status == 0 && lam > 0.0) ? cfl / lam : __builtin_nan("");
+  t->lam_bits = 0ull;
+}
+
+// ------------------------------------------------------------------------
+// Launchers.
+// ------------------------------------------------------------------------
+template <int DIM, bool MIXED, int STAGE>
+static hipError_t launch_k(int kmask, int grid, hipStream_t s, const StageArgs &a) {
+  switch (kmask) {
+    case 1:
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1>), dim3(grid), dim3(WG), 0, s, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2>), dim3(grid), dim3(WG), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3>), dim3(grid), dim3(WG), 0, s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int grid, hipStream_t s, const StageArgs &a) {
+  if (grid <= 0) return hipSuccess;
+  if (ndim == 2) {
+    if (mixed) return stage == 1 ? launch_k<2, true, 1>(kmask, grid, s, a) : launch_k<2, true, 2>(kmask, grid, s, a);
+    return stage == 1 ? launch_k<2, false, 1>(kmask, grid, s, a) : launch_k<2, false, 2>(kmask, grid, s, a);
+  }
+  if (mixed) return stage == 1 ? launch_k<3, true, 1>(kmask, grid, s, a) : launch_k<3, true, 2>(kmask, grid, s, a);
+  return stage == 1 ? launch_k<3, false, 1>(kmask, grid, s, a) : launch_k<3, false, 2>(kmask, grid, s, a);
+}
+
+hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a) {
+  if (grid <= 0) return hipSuccess;
+  const bool t16 = kmask & 1;
+  if (ndim == 2) {
+    if (t16)
+      hipLaunchKernelGGL((k_lambda<2, 3>), dim3(grid), dim3(WG), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_lambda<2, 2>), dim3(grid), dim3(WG), 0, s, a);
+  } else {
+    if (t16)
+      hipLaunchKernelGGL((k_lambda<3, 3>), dim3(grid), dim3(WG), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_lambda<3, 2>), dim3(grid), dim3(WG), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(DevTime *t, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, s, t, cfl, init);
+  return hipGetLastError();
+}
+
+}  // namespace hyd

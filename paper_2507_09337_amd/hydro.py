@@ -1,0 +1,231 @@
+"""ctypes binding of libhydro.so (C ABI in include/hydro.h).
+
+Argument marshalling only: every step of the hydro path runs in the HIP
+kernels of the library.  PyTorch supplies device memory and the stream.  The
+library is loaded on first use; if it is missing the call raises (there is no
+CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+HEADER = os.path.join(ROOT, "include", "hydro.h")
+
+OK, EINVAL, EDEVICE, ENOMEM, ENONPHYS, ESTATE = range(6)
+FP64, FP32_FP64 = 0, 1
+NBR, OUTFLOW, PERIODIC_SELF = 0, 1, 2
+_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "ENOMEM", 4: "ENONPHYS", 5: "ESTATE"}
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what}: {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class BlockDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("face_kind", C.c_int32 * 6),
+        ("nbr", C.c_int32 * 6),
+        ("reserved", C.c_int32),
+        ("offset", C.c_int64),
+        ("dx", C.c_double * 3),
+    ]
+
+
+def declared_functions() -> list:
+    """Names of the functions include/hydro.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:hydro_status|const char\s*\*)\s*(hydro_\w+)\s*\(", text, re.M)))
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with python -c "
+                               "'import __graft_entry__ as g; g.build()'")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        pp = C.POINTER(C.c_void_p)
+        sig = {
+            "hydro_mesh_create": [C.POINTER(BlockDesc), i32, i32, vp, i64, vp, pp],
+            "hydro_mesh_destroy": [vp],
+            "hydro_packet_create": [vp, C.POINTER(C.c_int32), i32, i32, pp],
+            "hydro_packet_advance": [vp, dbl, dbl],
+            "hydro_packet_reduce_dt": [vp, dbl, dbl, C.POINTER(C.c_double)],
+            "hydro_packet_destroy": [vp],
+            "hydro_batch_create": [C.POINTER(C.c_void_p), i32, pp],
+            "hydro_batch_advance_plain": [vp, dbl, dbl],
+            "hydro_batch_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
+            "hydro_batch_destroy": [vp],
+            "hydro_batch_set_tiling": [vp, i32, i32, i32],
+            "hydro_batch_set_grid": [vp, i32],
+            "hydro_batch_autotune": [vp, dbl, i32],
+            "hydro_batch_get_config": [vp, C.POINTER(C.c_int32), i32, C.POINTER(C.c_int32)],
+            "hydro_batch_time_kernels": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.hydro_last_error.restype = C.c_char_p
+        L.hydro_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise HydroError(rc, what, lib().hydro_last_error().decode())
+
+
+def descs_from_mesh(mesh) -> "C.Array":
+    """Block descriptors of an ``inputs.BlockMesh`` (or any object with the
+    same n, dx, kind, nbr, offset arrays)."""
+    nb = int(mesh.n.shape[0])
+    arr = (BlockDesc * nb)()
+    for b in range(nb):
+        d = arr[b]
+        for a in range(3):
+            d.n[a] = int(mesh.n[b, a])
+            d.dx[a] = float(mesh.dx[b, a])
+        for f in range(6):
+            d.face_kind[f] = int(mesh.kind[b, f])
+            d.nbr[f] = int(mesh.nbr[b, f])
+        d.reserved = 0
+        d.offset = int(mesh.offset[b])
+    return arr
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+class Mesh:
+    """A mesh over a caller-owned FP64 device arena (a torch tensor or a raw
+    device pointer with its length)."""
+
+    def __init__(self, block_mesh, arena, arena_len: int | None = None, stream=None):
+        self._keep = arena
+        if hasattr(arena, "data_ptr"):
+            import torch
+
+            if arena.dtype != torch.float64 or not arena.is_cuda or not arena.is_contiguous():
+                raise ValueError("arena must be a contiguous float64 CUDA tensor")
+            ptr, n = arena.data_ptr(), arena.numel()
+        else:
+            ptr, n = int(arena), int(arena_len)
+        self.block_mesh = block_mesh
+        self.ndim = int(block_mesh.ndim)
+        self._descs = descs_from_mesh(block_mesh)
+        h = C.c_void_p()
+        _check(lib().hydro_mesh_create(self._descs, len(self._descs), self.ndim, C.c_void_p(ptr), n,
+                                       C.c_void_p(_stream_handle(stream)), C.byref(h)), "hydro_mesh_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib().hydro_mesh_destroy(self.h), "hydro_mesh_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Packet:
+    def __init__(self, mesh: Mesh, block_ids, precision: int = FP64):
+        ids = np.ascontiguousarray(block_ids, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().hydro_packet_create(mesh.h, ids.ctypes.data_as(C.POINTER(C.c_int32)), int(ids.size),
+                                         int(precision), C.byref(h)), "hydro_packet_create")
+        self.mesh, self.h, self.ids, self.precision = mesh, h, ids, precision
+
+    def advance(self, dt: float, gamma: float):
+        _check(lib().hydro_packet_advance(self.h, float(dt), float(gamma)), "hydro_packet_advance")
+
+    def reduce_dt(self, gamma: float, cfl: float) -> float:
+        out = C.c_double(0.0)
+        _check(lib().hydro_packet_reduce_dt(self.h, float(gamma), float(cfl), C.byref(out)), "hydro_packet_reduce_dt")
+        return out.value
+
+    def close(self):
+        if self.h:
+            _check(lib().hydro_packet_destroy(self.h), "hydro_packet_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    def __init__(self, packets):
+        self.packets = list(packets)
+        arr = (C.c_void_p * len(self.packets))(*[p.h.value for p in self.packets])
+        h = C.c_void_p()
+        _check(lib().hydro_batch_create(arr, len(self.packets), C.byref(h)), "hydro_batch_create")
+        self.h = h
+
+    def advance_plain(self, dt: float, gamma: float):
+        _check(lib().hydro_batch_advance_plain(self.h, float(dt), float(gamma)), "hydro_batch_advance_plain")
+
+    def run(self, nsteps: int, cfl: float, gamma: float) -> float:
+        t = C.c_double(0.0)
+        _check(lib().hydro_batch_run(self.h, int(nsteps), float(cfl), float(gamma), C.byref(t)), "hydro_batch_run")
+        return t.value
+
+    def time_kernels(self, nsteps: int, cfl: float, gamma: float) -> dict:
+        """Eager launches with HIP events: mean stage-1 / stage-2 kernel ms and ms per step."""
+        out = (C.c_double * 3)()
+        _check(lib().hydro_batch_time_kernels(self.h, int(nsteps), float(cfl), float(gamma), out),
+               "hydro_batch_time_kernels")
+        return {"stage1_ms": out[0], "stage2_ms": out[1], "step_ms": out[2]}
+
+    def set_tiling(self, edge: int, tile: int, zchunk: int = 0):
+        _check(lib().hydro_batch_set_tiling(self.h, int(edge), int(tile), int(zchunk)), "hydro_batch_set_tiling")
+
+    def set_grid(self, grid: int):
+        _check(lib().hydro_batch_set_grid(self.h, int(grid)), "hydro_batch_set_grid")
+
+    def autotune(self, gamma: float, reps: int = 3):
+        _check(lib().hydro_batch_autotune(self.h, float(gamma), int(reps)), "hydro_batch_autotune")
+
+    def config(self) -> dict:
+        buf = (C.c_int32 * (1 + 4 * 16))()
+        n = C.c_int32(0)
+        _check(lib().hydro_batch_get_config(self.h, buf, 16, C.byref(n)), "hydro_batch_get_config")
+        classes = [{"edge": buf[1 + 4 * k], "tile": buf[2 + 4 * k], "zchunk": buf[3 + 4 * k], "cells": buf[4 + 4 * k]}
+                   for k in range(min(n.value, 16))]
+        return {"grid": buf[0], "classes": classes}
+
+    def close(self):
+        if self.h:
+            _check(lib().hydro_batch_destroy(self.h), "hydro_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/hydro.h declares, and rejects bad arguments on the host (before any
+device call) with HYDRO_EINVAL and a message."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2507_09337_amd import hydro as H
+from paper_2507_09337_amd import inputs as I
+
+FAKE_ARENA = C.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def test_library_exports_every_declared_function():
+    names = H.declared_functions()
+    assert len(names) >= 15
+    L = H.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _create(mesh, ndim=None, arena_len=None, arena=FAKE_ARENA):
+    descs = H.descs_from_mesh(mesh)
+    h = C.c_void_p()
+    rc = H.lib().hydro_mesh_create(descs, len(descs), mesh.ndim if ndim is None else ndim, arena,
+                                   mesh.arena_len if arena_len is None else arena_len, None, C.byref(h))
+    return rc, H.lib().hydro_last_error().decode()
+
+
+def good():
+    return I.block_grid((2, 2, 1), (16, 16, 4), (0, 0, 0), (1, 1, 1), "periodic", 3)
+
+
+@pytest.mark.parametrize(
+    "mutate,needle",
+    [
+        (lambda m: m.n.__setitem__((0, 0), 12), "multiples of 8"),
+        (lambda m: m.kind.__setitem__((1, 2), 7), "face kind"),
+        (lambda m: m.nbr.__setitem__((2, 1), 99), "out of range"),
+        (lambda m: m.offset.__setitem__(1, 3), "overlap"),
+        (lambda m: m.offset.__setitem__(3, 10**9), "outside the arena"),
+        (lambda m: m.dx.__setitem__((0, 1), -1.0), "dx"),
+        (lambda m: m.dx.__setitem__((0, 2), float("nan")), "dx"),
+        (lambda m: m.n.__setitem__((0, 2), 1), "n[2]"),
+    ],
+)
+def test_bad_descriptor_rejected_on_host(mutate, needle):
+    m = good()
+    arena_len = m.arena_len
+    mutate(m)
+    rc, msg = _create(m, arena_len=arena_len)
+    assert rc == H.EINVAL and needle in msg, msg
+
+
+def test_valid_mesh_without_gpu_fails_loudly_or_succeeds():
+    """A valid descriptor passes host validation; with no GPU the call must
+    then fail with EDEVICE (never silently succeed on the CPU)."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = _create(good())
+    assert rc == H.EDEVICE and msg
+
+
+def test_tangential_mismatch_rejected():
+    m = I.independent_blocks([16, 16], 3)
+    m.kind[0, 0] = I.NBR
+    m.nbr[0, 0] = 1
+    m.n[1] = (16, 16, 8)  # tangential z extent differs
+    m.offset[1] = 5 * 16 ** 3
+    rc, msg = _create(m)
+    assert rc == H.EINVAL and "tangential" in msg
+
+
+def test_2d_requires_unit_z():
+    m = I.block_grid((2, 1, 1), (16, 16, 1), (0, 0, 0), (1, 1, 1), "outflow", 2)
+    m.n[0, 2] = 2
+    rc, msg = _create(m, ndim=2)
+    assert rc == H.EINVAL and "2D" in msg
+
+
+def test_bad_ndim_null_arena_and_null_handles():
+    m = good()
+    assert _create(m, ndim=4)[0] == H.EINVAL
+    assert _create(m, arena=C.c_void_p(None))[0] == H.EINVAL
+    assert _create(m, arena_len=0)[0] == H.EINVAL
+    L = H.lib()
+    out = C.c_void_p()
+    ids = (C.c_int32 * 1)(0)
+    assert L.hydro_packet_create(None, ids, 1, 0, C.byref(out)) == H.EINVAL
+    assert L.hydro_packet_advance(None, 1e-3, 1.4) == H.EINVAL
+    assert L.hydro_batch_run(None, 1, 0.4, 1.4, None) == H.EINVAL
+    assert L.hydro_batch_create(None, 0, C.byref(out)) == H.EINVAL
+    assert L.hydro_mesh_destroy(None) == H.EINVAL
+    assert L.hydro_last_error()  # a message is set

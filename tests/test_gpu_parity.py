@@ -1,0 +1,228 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP64 path <= 1e-12 relative per cell (floored: the denominator is
+max(|ref|, 1e-6 max|ref| of that variable), so a momentum crossing zero is
+compared on the field's scale); mixed FP32/FP64 path L1(rho) <= 1e-5 relative
+on smooth flow.  Bitwise invariants (uniform state, 2D row identity) hold
+exactly on the GPU as in the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import l1_rho, rel_err, to_dev, to_host
+from oracle import oracle as O
+from paper_2507_09337_amd import hydro as H
+from paper_2507_09337_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL_L1_MIXED = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def oracle_run(P, nsteps, fixed_dt=0.0):
+    R = P.U0.copy()
+    dts, t = O.run(P.mesh, R, nsteps, P.cfl, P.gamma, fixed_dt)
+    return R, dts, t
+
+
+# ------------------------------------------------------------------- C1 Sod
+def test_sod2d_packet_path_fp64():
+    P = I.sod2d()
+    R, dts, t_ref = oracle_run(P, P.nsteps)
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    pk = H.Packet(mesh, range(P.mesh.nblocks), H.FP64)
+    for s in range(P.nsteps):
+        dt = pk.reduce_dt(P.gamma, P.cfl)
+        assert abs(dt - dts[s]) <= TOL64 * dts[s], (s, dt, dts[s])
+        pk.advance(dt, P.gamma)
+    U = to_host(arena)
+    assert rel_err(P.mesh, U, R) <= TOL64
+
+
+def test_sod2d_graph_path_fp64_and_rows():
+    P = I.sod2d()
+    R, dts, t_ref = oracle_run(P, P.nsteps)
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), H.FP64)])
+    t = b.run(P.nsteps, P.cfl, P.gamma)
+    U = to_host(arena)
+    assert abs(t - t_ref) <= TOL64 * t_ref
+    assert rel_err(P.mesh, U, R) <= TOL64
+    # bitwise: every row identical, rho*v exactly 0
+    for blk in range(P.mesh.nblocks):
+        f = P.mesh.block_view(U, blk)
+        assert np.all(f[2] == 0.0)
+        assert all(np.array_equal(f[0, 0, 0], f[0, 0, j]) for j in range(f.shape[2]))
+
+
+# ----------------------------------------------------------- uniform states
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
+@pytest.mark.parametrize(
+    "mk",
+    [
+        lambda: I.block_grid((2, 2, 1), (16, 16, 1), (0, 0, 0), (1, 1, 1), "outflow", 2),
+        lambda: I.block_grid((2, 1, 2), (16, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3),
+        lambda: I.block_grid((1, 2, 1), (32, 16, 6), (0, 0, 0), (1, 1, 1), "outflow", 3),
+        lambda: I.independent_blocks([8, 16, 32], 3),
+    ],
+    ids=["2d-outflow", "3d-periodic", "3d-outflow-thin", "3d-selfperiodic"],
+)
+def test_uniform_state_bitwise(mk, prec):
+    mesh_ = mk()
+    U0 = I.uniform_state(mesh_, rho=1.3, vel=(0.3, -0.2, 0.1), p=0.7, gamma=1.4)
+    arena = to_dev(U0)
+    mesh = H.Mesh(mesh_, arena)
+    b = H.Batch([H.Packet(mesh, range(mesh_.nblocks), prec)])
+    b.run(4, 0.4, 1.4)
+    b.advance_plain(1e-3, 1.4)
+    assert np.array_equal(to_host(arena), U0)
+
+
+# ------------------------------------------------------------- C2 Sedov
+@pytest.fixture(scope="module")
+def sedov():
+    P = I.sedov3d()
+    R, dts, t = oracle_run(P, P.nsteps)
+    return P, R, dts, t
+
+
+def test_sedov_plain_per_packet_fp64(sedov):
+    P, R, dts, t_ref = sedov
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    pks = [H.Packet(mesh, ids, H.FP64) for ids in P.packets]
+    b = H.Batch(pks)
+    for s in range(P.nsteps):
+        dt = min(pk.reduce_dt(P.gamma, P.cfl) for pk in pks)
+        assert abs(dt - dts[s]) <= TOL64 * dts[s], (s, dt, dts[s])
+        b.advance_plain(dt, P.gamma)
+    U = to_host(arena)
+    assert rel_err(P.mesh, U, R) <= TOL64
+
+
+def test_sedov_graph_fp64_conservation_and_mirror(sedov):
+    P, R, dts, t_ref = sedov
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    b = H.Batch([H.Packet(mesh, ids, H.FP64) for ids in P.packets])
+    t = b.run(P.nsteps, P.cfl, P.gamma)
+    U = to_host(arena)
+    assert abs(t - t_ref) <= TOL64 * t_ref
+    assert rel_err(P.mesh, U, R) <= TOL64
+    # conservation of the totals (periodic mesh)
+    vol = float(np.prod(P.mesh.dx[0]))
+    for v in range(5):
+        a = P.U0.reshape(P.mesh.nblocks, 5, -1)[:, v].ravel()
+        c = U.reshape(P.mesh.nblocks, 5, -1)[:, v].ravel()
+        assert abs(math.fsum(c) - math.fsum(a)) * vol <= 1e-13 * P.nsteps * math.fsum(np.abs(a)) * vol
+    # mirror symmetry about x = 1/2 of the centred blast
+    from test_oracle_scheme import assemble
+
+    rho = assemble(P.mesh, U, 0)
+    assert np.abs(np.flip(rho, axis=2) - rho).max() <= 1e-12 * np.abs(rho).max()
+
+
+# ------------------------------------------------------ C3 smooth (reduced)
+@pytest.mark.parametrize("tile,zchunk", [(0, 0), (1, 0), (0, 4)], ids=["t16", "t8", "t16-z4"])
+def test_smooth_fp64_and_mixed(tile, zchunk):
+    P = I.smooth3d(nblk=(4, 4, 4), nsteps=30)
+    R, dts, t_ref = oracle_run(P, P.nsteps)
+    for prec, check in ((H.FP64, "rel"), (H.FP32_FP64, "l1")):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+        b.set_tiling(16, tile, zchunk)
+        t = b.run(P.nsteps, P.cfl, P.gamma)
+        U = to_host(arena)
+        if check == "rel":
+            assert rel_err(P.mesh, U, R) <= TOL64
+            assert abs(t - t_ref) <= TOL64 * t_ref
+        else:
+            assert l1_rho(P.mesh, U, R) <= TOL_L1_MIXED
+        b.close()
+        mesh.close()
+
+
+# ------------------------------------------------------- C4 uneven (reduced)
+def test_uneven_fp64_and_mixed_autotuned():
+    P = I.uneven(nblocks=120, nsteps=20)
+    R, dts, t_ref = oracle_run(P, P.nsteps)
+    for prec in (H.FP64, H.FP32_FP64):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+        b.autotune(P.gamma, reps=2)
+        cfg = b.config()
+        assert {c["edge"] for c in cfg["classes"]} == {8, 16, 32}
+        t = b.run(P.nsteps, P.cfl, P.gamma)
+        U = to_host(arena)
+        if prec == H.FP64:
+            assert rel_err(P.mesh, U, R) <= TOL64
+            assert abs(t - t_ref) <= TOL64 * t_ref
+        else:
+            assert l1_rho(P.mesh, U, R) <= TOL_L1_MIXED
+        b.close()
+        mesh.close()
+
+
+# -------------------------------------------------------------- errors
+def test_nonphysical_state_reported():
+    m = I.block_grid((2, 1, 1), (16, 16, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    U0 = I.uniform_state(m, gamma=1.4)
+    m.block_view(U0, 1)[4, 3, 5, 7] = 0.0  # E < rho|v|^2/2
+    arena = to_dev(U0)
+    mesh = H.Mesh(m, arena)
+    pk = H.Packet(mesh, range(m.nblocks), H.FP64)
+    with pytest.raises(H.HydroError) as e:
+        pk.reduce_dt(1.4, 0.4)
+    assert e.value.code == H.ENONPHYS and "block 1" in str(e.value)
+    b = H.Batch([pk])
+    with pytest.raises(H.HydroError) as e:
+        b.run(2, 0.4, 1.4)
+    assert e.value.code == H.ENONPHYS
+
+
+def test_open_packet_refuses_advance_and_batch_is_stage_synchronous():
+    m = I.block_grid((2, 1, 1), (16, 16, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    U0 = I.random_smooth_state(m, 3, 1.4)
+    arena = to_dev(U0)
+    mesh = H.Mesh(m, arena)
+    p0, p1 = H.Packet(mesh, [0], H.FP64), H.Packet(mesh, [1], H.FP64)
+    with pytest.raises(H.HydroError) as e:
+        p0.advance(1e-3, 1.4)
+    assert e.value.code == H.ESTATE
+    b = H.Batch([p0, p1])
+    b.advance_plain(1e-3, 1.4)
+    R = U0.copy()
+    O.step(m, R, 1e-3, 1.4)
+    assert rel_err(m, to_host(arena), R) <= TOL64
+
+
+def test_deterministic_bitwise():
+    P = I.smooth3d(nblk=(2, 2, 2), nsteps=5)
+    outs = []
+    for _ in range(2):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), H.FP32_FP64)])
+        b.run(P.nsteps, P.cfl, P.gamma)
+        outs.append(to_host(arena))
+        b.close()
+        mesh.close()
+    assert np.array_equal(outs[0], outs[1])
