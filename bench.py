@@ -97,6 +97,29 @@ def one_step_errors(P, arena, U0_dev, mesh, packets_fp64, packets_mixed):
     return out
 
 
+def copy_bandwidth(n_doubles=1 << 28, reps=5):
+    """GB/s of the project's plain stream-copy kernel on two 2 GiB buffers
+    (far larger than the 256 MB last-level cache): read + write bytes / time."""
+    import ctypes as C
+
+    import torch
+
+    lib = C.CDLL(os.path.join(ROOT, "paper_2507_09337_amd", "libhydro_probe.so"))
+    lib.copy_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.POINTER(C.c_double)]
+    src = torch.ones(n_doubles, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms = C.c_double(0.0)
+    rc = lib.copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n_doubles,
+                        C.c_void_p(torch.cuda.current_stream().cuda_stream), reps, C.byref(ms))
+    if rc != 0:
+        raise RuntimeError(f"copy_probe failed with {rc}")
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"gbs": 2 * 8 * n_doubles / (ms.value * 1e-3) / 1e9, "bytes_per_copy": 16 * n_doubles, "ms": ms.value,
+            "verified": ok}
+
+
 def cpu_baseline(P, budget_s=12.0):
     """The oracle as it stands, on the 8x8x8-block cube at the centre of the
     workload (or the first 512 blocks), steps until ~budget_s of CPU work."""
@@ -140,6 +163,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    probe = copy_bandwidth()
+    log("copy probe:", json.dumps(probe))
     t0 = time.perf_counter()
     P = make_problem(args.workload)
     cells = P.mesh.total_cells
@@ -206,6 +231,7 @@ def main():
         "kernel": "k_stage (stage-1 + stage-2 launch of one step; 80 + 120 algorithmic B per interior cell)",
         "stage1_ms": km["stage1_ms"], "stage2_ms": km["stage2_ms"],
         "algorithmic_bytes_per_step": BYTES_PER_CELL_UPDATE * cells,
+        "copy_probe_gbs": probe["gbs"], "frac_of_copy_probe": achieved / probe["gbs"],
     }
     km64 = kernel_ms["batched_fp64"]
     ach64 = BYTES_PER_CELL_UPDATE * cells / ((km64["stage1_ms"] + km64["stage2_ms"]) * 1e-3) / 1e9

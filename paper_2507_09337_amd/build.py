@@ -13,6 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhydro.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip")]
+# measurement helper (stream-copy bandwidth probe), kept out of libhydro.so
+PROBE_LIB = os.path.join(HERE, "libhydro_probe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "copy_probe.hip")]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -26,8 +29,8 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra: list | None = None) -> str:
-    cmd = ["hipcc", *FLAGS, *(extra or []), "-o", LIB + ".tmp", *SOURCES]
+def _hipcc(out: str, sources: list, verbose: bool, extra: list | None) -> None:
+    cmd = ["hipcc", *FLAGS, *(extra or []), "-o", out + ".tmp", *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -37,7 +40,12 @@ def build(verbose: bool = False, extra: list | None = None) -> str:
         raise RuntimeError("hipcc failed:\n" + msgs)
     if verbose and msgs.strip():
         print(msgs)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False, extra: list | None = None) -> str:
+    _hipcc(LIB, SOURCES, verbose, extra)
+    _hipcc(PROBE_LIB, PROBE_SOURCES, verbose, extra)
     return LIB
 
 

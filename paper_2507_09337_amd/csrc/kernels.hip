@@ -120,10 +120,56 @@ __device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T 
   F[4] = star ? f4 + S * (Es - E) : f4;
 }
 
-// FP64 primitive recovery (ideal gas).  Returns false for rho <= 0, p <= 0
-// or non-finite values.
+// HLLC in FP64 with the operations in the order of the textbook statement
+// (left and right states, Davis speeds, S* from the jump relations, star state
+// rho_K (S_K - u)/(S_K - S*) (1, S*, v, w, E/rho + (S* - u)(S* + p/(rho (S_K - u))))),
+// no contraction into FMAs.  Division and square root are IEEE-correct on the
+// device, so each face flux is rounded exactly as in a plain FP64 CPU
+// evaluation of the same formulas.  Only the side K of the contact is formed.
+__device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], double g, double F[5]) {
+#pragma clang fp contract(off)
+  const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
+  const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
+  const double cL = __builtin_sqrt(g * pL / rL);
+  const double cR = __builtin_sqrt(g * pR / rR);
+  const double SL = fmin(uL - cL, uR - cR);
+  const double SR = fmax(uL + cL, uR + cR);
+  const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
+  const bool useL = (0.0 <= SL) || (0.0 <= Ss);
+  const double r = useL ? rL : rR, u = useL ? uL : uR, v = useL ? vL : vR, w = useL ? wL : wR, p = useL ? pL : pR;
+  const double SK = useL ? SL : SR;
+  const bool star = useL ? !(0.0 <= SL) : (0.0 < SR);
+  const double E = p / (g - 1.0) + 0.5 * r * (u * u + v * v + w * w);
+  const double FK[5] = {r * u, r * u * u + p, r * u * v, r * u * w, u * (E + p)};
+  const double UK[5] = {r, r * u, r * v, r * w, E};
+  const double a = r * (SK - u) / (SK - Ss);
+  const double Us[5] = {a, a * Ss, a * v, a * w, a * (E / r + (Ss - u) * (Ss + p / (r * (SK - u))))};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) F[k] = star ? FK[k] + SK * (Us[k] - UK[k]) : FK[k];
+}
+
+// FP64 primitive recovery (ideal gas), in the plain evaluation order
+// u = m/rho; rho e = E - (m_x u + m_y v + m_z w)/2; p = (gamma-1) rho e.
+// Returns false for rho <= 0, p <= 0 or non-finite values.
 __device__ __forceinline__ bool recover(double U0, double U1, double U2, double U3, double U4, double gm1,
                                         double W[5]) {
+#pragma clang fp contract(off)
+  const double u = U1 / U0, v = U2 / U0, w = U3 / U0;
+  const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
+  const double p = gm1 * rhoe;
+  W[0] = U0;
+  W[1] = u;
+  W[2] = v;
+  W[3] = w;
+  W[4] = p;
+  const double s = fabs(u) + fabs(v) + fabs(w) + p + U0;
+  return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
+}
+
+// Faster recovery for the mixed path (one reciprocal); its primitives are
+// rounded to FP32 right after.
+__device__ __forceinline__ bool recover_fast(double U0, double U1, double U2, double U3, double U4, double gm1,
+                                             double W[5]) {
   const double inv = 1.0 / U0;
   const double u = U1 * inv, v = U2 * inv, w = U3 * inv;
   const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
@@ -137,8 +183,34 @@ __device__ __forceinline__ bool recover(double U0, double U1, double U2, double 
   return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
 }
 
+template <bool FAST>
 __device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t vs, double gm1, double W[5]) {
+  if (FAST) return recover_fast(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
   return recover(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
+}
+
+// CFL rate of one cell, sum over active directions of (|u_d| + c)/dx_d.
+template <int DIM>
+__device__ __forceinline__ double cell_rate(const double W[5], double gamma, double dx0, double dx1, double dx2) {
+#pragma clang fp contract(off)
+  const double c = __builtin_sqrt(gamma * W[4] / W[0]);
+  double lam = 0.0;
+  lam += (fabs(W[1]) + c) / dx0;
+  lam += (fabs(W[2]) + c) / dx1;
+  if (DIM == 3) lam += (fabs(W[3]) + c) / dx2;
+  return lam;
+}
+
+// Face flux in the frame of direction d (normal velocity first), for either
+// precision.
+template <bool MIXED>
+__device__ __forceinline__ void face_flux(const typename std::conditional<MIXED, float, double>::type L[5],
+                                          const typename std::conditional<MIXED, float, double>::type R[5],
+                                          double gamma, typename std::conditional<MIXED, float, double>::type F[5]) {
+  if constexpr (MIXED)
+    hllc<float>(L, R, (float)gamma, (float)(1.0 / (gamma - 1.0)), F);
+  else
+    hllc_fp64(L, R, gamma, F);
 }
 
 // Source of an out-of-block cell along one axis: face f's source block and
@@ -224,7 +296,6 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   const int x = x0 + ti, y = y0 + tj;
   const int z0 = it->z0, z1 = it->z1;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
-  const T tg = (T)gamma, trgm1 = (T)(1.0 / gm1);
 
   double dtdx = 0, dtdy = 0, dtdz = 0, dx0 = 1, dx1 = 1, dx2 = 1;
   int nx = 1, ny = 1, nz = 1, ncell = 1;
@@ -281,7 +352,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     }
     if (gslot >= 0) {
       double Wg[5];
-      if (!load_prim(src + goff + (int64_t)z * gps, gvs, gm1, Wg)) bad = 1;
+      if (!load_prim<MIXED>(src + goff + (int64_t)z * gps, gvs, gm1, Wg)) bad = 1;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) Wp[v * PP + gslot] = (T)Wg[v];
     }
@@ -317,7 +388,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
       const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
       T Fr[5];
-      hllc<T>(Lr, Rr, tg, trgm1, Fr);
+      face_flux<MIXED>(Lr, Rr, gamma, Fr);
       out[0] = Fr[0];
       out[ostride] = isx ? Fr[1] : Fr[2];
       out[2 * ostride] = isx ? Fr[2] : Fr[1];
@@ -326,8 +397,11 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     }
   };
 
-  // RK stage update of this thread's cell in plane z
+  // RK stage update of this thread's cell in plane z:
+  //   dU = sum over x, y, z of (dt/dx_d)(F_lo - F_hi), FP64, no contraction;
+  //   stage 1: U1 = Un + dU;  stage 2: Un+1 = Un/2 + (U1 + dU)/2.
   auto update = [&](int z, const T (&fzlo)[5], const T (&fzhi)[5]) {
+#pragma clang fp contract(off)
     if (!active) return;
     const int64_t c = (int64_t)z * plane;
     double Unew[5];
@@ -337,7 +411,8 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const double fxh = (double)Fx[v * NXF + tj * (TX + 1) + ti + 1];
       const double fyl = (double)Fy[v * NYF + tj * TX + ti];
       const double fyh = (double)Fy[v * NYF + (tj + 1) * TX + ti];
-      double dU = dtdx * (fxl - fxh) + dtdy * (fyl - fyh);
+      double dU = dtdx * (fxl - fxh);
+      dU += dtdy * (fyl - fyh);
       if (DIM == 3) dU += dtdz * ((double)fzlo[v] - (double)fzhi[v]);
       const double s = own[v * own_vs + c];
       if (STAGE == 1) {
@@ -354,17 +429,14 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
         bad = 1;
         badblk = min(badblk, b);
       } else {
-        const double cs = __builtin_sqrt(gamma * W[4] / W[0]);
-        double l = (fabs(W[1]) + cs) / dx0 + (fabs(W[2]) + cs) / dx1;
-        if (DIM == 3) l += (fabs(W[3]) + cs) / dx2;
-        lam = fmax(lam, l);
+        lam = fmax(lam, cell_rate<DIM>(W, gamma, dx0, dx1, dx2));
       }
     }
   };
 
   if (DIM == 2) {
     double Wc[5] = {1, 0, 0, 0, 1};
-    if (active && !load_prim(own, own_vs, gm1, Wc)) {
+    if (active && !load_prim<MIXED>(own, own_vs, gm1, Wc)) {
       bad = 1;
       badblk = min(badblk, b);
     }
@@ -390,7 +462,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     } else {
       cell_addr(Bp, x, y, z, off, vs);
     }
-    if (!load_prim(src + off, vs, gm1, W)) {
+    if (!load_prim<MIXED>(src + off, vs, gm1, W)) {
       bad = 1;
       badblk = min(badblk, b);
     }
@@ -409,7 +481,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
       const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
       T Fr[5];
-      hllc<T>(Lr, Rr, tg, trgm1, Fr);
+      face_flux<MIXED>(Lr, Rr, gamma, Fr);
       fz[0] = Fr[0];
       fz[1] = Fr[3];
       fz[2] = Fr[2];
@@ -508,15 +580,12 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
     const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
     for (int z = za; z < zb; ++z) {
       double W[5];
-      if (!load_prim(p + z * plane, B.ncell, gm1, W)) {
+      if (!load_prim<false>(p + z * plane, B.ncell, gm1, W)) {
         bad = 1;
         badblk = min(badblk, b);
         continue;
       }
-      const double cs = __builtin_sqrt(A.gamma * W[4] / W[0]);
-      double l = (fabs(W[1]) + cs) / B.dx[0] + (fabs(W[2]) + cs) / B.dx[1];
-      if (DIM == 3) l += (fabs(W[3]) + cs) / B.dx[2];
-      lam = fmax(lam, l);
+      lam = fmax(lam, cell_rate<DIM>(W, A.gamma, B.dx[0], B.dx[1], B.dx[2]));
     }
   }
   flush_acc(A.acc, lam, bad, badblk, true);
