@@ -150,6 +150,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-packet FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tune", action="store_true", help="autotune the batched launches first")
+    ap.add_argument("--no-check", action="store_true", help="skip the one-step error check against the oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -178,7 +179,7 @@ def main():
     pkmx = [H.Packet(mesh, ids, H.FP32_FP64) for ids in P.packets]
     log(f"{len(P.packets)} packets")
 
-    errs = one_step_errors(P, arena, U0_dev, mesh, pk64, pkmx)
+    errs = None if args.no_check else one_step_errors(P, arena, U0_dev, mesh, pk64, pkmx)
     log("one-step errors vs oracle:", json.dumps(errs))
 
     results = {}

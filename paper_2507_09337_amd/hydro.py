@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -133,6 +134,7 @@ class Mesh:
             ptr, n = int(arena), int(arena_len)
         self.block_mesh = block_mesh
         self.ndim = int(block_mesh.ndim)
+        self._children = weakref.WeakSet()  # live packets and batches, closed before the mesh
         self._descs = descs_from_mesh(block_mesh)
         h = C.c_void_p()
         _check(lib().hydro_mesh_create(self._descs, len(self._descs), self.ndim, C.c_void_p(ptr), n,
@@ -141,6 +143,13 @@ class Mesh:
 
     def close(self):
         if self.h:
+            kids = list(self._children)
+            for c in kids:
+                if isinstance(c, Batch):
+                    c.close()
+            for c in kids:
+                if isinstance(c, Packet):
+                    c.close()
             _check(lib().hydro_mesh_destroy(self.h), "hydro_mesh_destroy")
             self.h = None
 
@@ -158,6 +167,7 @@ class Packet:
         _check(lib().hydro_packet_create(mesh.h, ids.ctypes.data_as(C.POINTER(C.c_int32)), int(ids.size),
                                          int(precision), C.byref(h)), "hydro_packet_create")
         self.mesh, self.h, self.ids, self.precision = mesh, h, ids, precision
+        mesh._children.add(self)
 
     def advance(self, dt: float, gamma: float):
         _check(lib().hydro_packet_advance(self.h, float(dt), float(gamma)), "hydro_packet_advance")
@@ -186,6 +196,7 @@ class Batch:
         h = C.c_void_p()
         _check(lib().hydro_batch_create(arr, len(self.packets), C.byref(h)), "hydro_batch_create")
         self.h = h
+        self.packets[0].mesh._children.add(self)
 
     def advance_plain(self, dt: float, gamma: float):
         _check(lib().hydro_batch_advance_plain(self.h, float(dt), float(gamma)), "hydro_batch_advance_plain")
