@@ -178,20 +178,24 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  *               multiples of 16); 1 = 8x8 tiles, four per workgroup;
  *   zchunk: z planes per work item (0 = the whole block; 3D only).
  * Per batch, grid = workgroups per stage launch (0 = one per work item; else a
- * persistent grid of that many workgroups looping over the work list).
- * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_grid
+ * persistent grid of that many workgroups looping over the work list), and
+ * xcd_remap = 1 renumbers workgroups so that each of the GPU's 8 XCDs (each
+ * with its own L2) runs a contiguous span of the work list, keeping
+ * neighbouring blocks' guard reads in one L2 (0 = hardware order).
+ * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_launch
  * rebuild or relaunch accordingly (EINVAL for a tile the class cannot use, or
- * a negative value).  hydro_batch_autotune times every candidate tiling of
+ * a value out of range).  hydro_batch_autotune times every candidate tiling of
  * every class present (stage-1 launches on the class's own blocks; they write
  * only the mesh's scratch stage buffer, never the arena), rejects a candidate
  * whose stage-1 result differs from the default tiling's by more than 1e-13
  * relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the fastest, then
- * picks the grid the same way.  reps = timed launches per candidate (>= 1).
- * Synchronising.  hydro_batch_get_config writes grid to out[0] and then
- * (edge, tile, zchunk, ncells_in_class_low32) for each class, up to
- * nclass_max classes; *nclass receives the number of classes. */
+ * picks grid and xcd_remap the same way.  reps = timed launches per candidate
+ * (>= 1).  Synchronising.  hydro_batch_get_config writes grid to out[0],
+ * xcd_remap to out[1], then (edge, tile, zchunk, ncells_in_class_low31) for
+ * each class from out[2], up to nclass_max classes (out holds 2 + 4 *
+ * nclass_max int32); *nclass receives the number of classes. */
 hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk);
-hydro_status hydro_batch_set_grid(hydro_batch *b, int32_t grid);
+hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_remap);
 hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps);
 hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass);
 

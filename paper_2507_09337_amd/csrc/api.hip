@@ -94,6 +94,7 @@ struct hydro_batch {
   int prec = HYDRO_FP64;
   std::map<int, TileCfg> cfg;
   int grid = 0;
+  int remap = 1;
   WorkList wl;
   DevTime *d_time = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -271,8 +272,9 @@ hydro_status alloc_time(DevTime **out, hipStream_t s) {
 }
 
 StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double dt, const DevTime *dt_dev,
-                     DevTime *acc, double gamma, int reset) {
+                     DevTime *acc, double gamma, int reset, int remap = 1) {
   StageArgs a;
+  a.xcd_remap = remap;
   a.blocks = m->d_blocks;
   a.items = wl.d_items;
   a.nitems = wl.nitems;
@@ -558,10 +560,10 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   const bool mixed = b->prec == HYDRO_FP32_FP64;
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hydro_status st =
-      launch_stage_wl(m, mixed, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0));
+      launch_stage_wl(m, mixed, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
   if (!st)
     st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, b->cap_stream,
-                         stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0));
+                         stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
   if (!st && hyd::launch_finalize(b->d_time, cfl, 0, b->cap_stream) != hipSuccess)
     st = fail(HYDRO_EDEVICE, "finalize launch failed");
   hipGraph_t g = nullptr;
@@ -597,7 +599,7 @@ hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double 
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
     e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
-                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0));
+                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
   for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(b->gexec, m->stream));
@@ -620,7 +622,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
     e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
-                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0));
+                           stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
   std::vector<hipEvent_t> ev(3 * nsteps + 1, nullptr);
@@ -628,10 +630,10 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   hydro_status st = HYDRO_OK;
   HIP_TRY(hipEventRecord(ev[0], m->stream));
   for (int s = 0; s < nsteps && !st; ++s) {
-    st = launch_stage_wl(m, mixed, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0));
+    st = launch_stage_wl(m, mixed, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
     if (!st && hipEventRecord(ev[3 * s + 1], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st)
-      st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0));
+      st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
     if (!st && hipEventRecord(ev[3 * s + 2], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st && hyd::launch_finalize(b->d_time, cfl, 0, m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "finalize");
     if (!st && hipEventRecord(ev[3 * s + 3], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
@@ -672,11 +674,13 @@ hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, 
   return rebuild_batch_items(b);
 }
 
-hydro_status hydro_batch_set_grid(hydro_batch *b, int32_t grid) {
+hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_remap) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
   if (grid < 0) return fail(HYDRO_EINVAL, "grid must be >= 0");
-  if (grid != b->grid) {
+  if (xcd_remap != 0 && xcd_remap != 1) return fail(HYDRO_EINVAL, "xcd_remap must be 0 or 1");
+  if (grid != b->grid || xcd_remap != b->remap) {
     b->grid = grid;
+    b->remap = xcd_remap;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
@@ -693,6 +697,7 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
     cells[block_class(d, b->m->ndim)] += (int64_t)d.n[0] * d.n[1] * d.n[2];
   }
   out[0] = b->grid;
+  out[1] = b->remap;
   int k = 0;
   for (auto &kv : cells) {
     if (k < nclass_max) {
@@ -706,10 +711,10 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
           break;
         }
       const bool can16 = any && any->n[0] % 16 == 0 && any->n[1] % 16 == 0;
-      out[1 + 4 * k + 0] = kv.first;
-      out[1 + 4 * k + 1] = (can16 && c.tile != 1) ? 0 : 1;
-      out[1 + 4 * k + 2] = c.zchunk;
-      out[1 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
+      out[2 + 4 * k + 0] = kv.first;
+      out[2 + 4 * k + 1] = (can16 && c.tile != 1) ? 0 : 1;
+      out[2 + 4 * k + 2] = c.zchunk;
+      out[2 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
     }
     ++k;
   }
@@ -718,7 +723,8 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
 }
 
 // Median time of `reps` stage-1 launches of a work list (ms).
-static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, double gamma, int reps, double &ms) {
+static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
+                                double &ms) {
   hydro_mesh *m = b->m;
   const bool mixed = b->prec == HYDRO_FP32_FP64;
   hipEvent_t e0, e1;
@@ -727,7 +733,7 @@ static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, do
   std::vector<double> t;
   hydro_status st = HYDRO_OK;
   const double dt = 1e-30;  // the result is scratch; any positive dt
-  StageArgs a = stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0);
+  StageArgs a = stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0, remap);
   st = launch_stage_wl(m, mixed, 1, wl, grid, m->stream, a);  // warm-up
   for (int r = 0; r < reps && !st; ++r) {
     (void)hipEventRecord(e0, m->stream);
@@ -826,7 +832,7 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
       st = upload_items(items, kmask, wl, m->stream);
       if (st) return st;
       double ms = 0;
-      st = time_stage1(b, wl, 0, gamma, reps, ms);
+      st = time_stage1(b, wl, 0, b->remap, gamma, reps, ms);
       (void)hipFree(wl.d_items);
       if (st) return st;
       if (ms < best) {
@@ -838,20 +844,23 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
   }
   hydro_status st = rebuild_batch_items(b);
   if (st) return st;
-  // grid: one workgroup per item, or persistent grids of k workgroups per CU
+  // launch: one workgroup per item or persistent grids of k workgroups per CU,
+  // each with and without the XCD renumbering
   double best = 1e300;
-  int bestg = 0;
-  for (int g : {0, 2 * m->num_cu, 4 * m->num_cu, 8 * m->num_cu}) {
-    if (g > 0 && g >= b->wl.nitems) continue;
-    double ms = 0;
-    st = time_stage1(b, b->wl, g, gamma, reps, ms);
-    if (st) return st;
-    if (ms < best) {
-      best = ms;
-      bestg = g;
+  int bestg = 0, bestr = 1;
+  for (int r : {1, 0})
+    for (int g : {0, 2 * m->num_cu, 4 * m->num_cu, 8 * m->num_cu}) {
+      if (g > 0 && g >= b->wl.nitems) continue;
+      double ms = 0;
+      st = time_stage1(b, b->wl, g, r, gamma, reps, ms);
+      if (st) return st;
+      if (ms < best) {
+        best = ms;
+        bestg = g;
+        bestr = r;
+      }
     }
-  }
-  return hydro_batch_set_grid(b, bestg);
+  return hydro_batch_set_launch(b, bestg, bestr);
 }
 
 }  // extern "C"

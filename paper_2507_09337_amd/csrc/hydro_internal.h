@@ -47,8 +47,6 @@ struct DevTime {
   unsigned long long lam_bits;  // max CFL rate as the bits of a non-negative double
   int32_t status;               // nonzero: a non-physical state was seen
   int32_t bad_block;            // smallest block id with a non-physical state
-  uint32_t wq_next;             // dynamic work queue: next item
-  uint32_t wq_done;             // dynamic work queue: workgroups finished
 };
 
 struct StageArgs {
@@ -56,6 +54,7 @@ struct StageArgs {
   const WorkItem *items;
   int32_t nitems;
   int32_t reset_time;  // 1: workgroup 0 clears lam/status of `acc` first (plain path)
+  int32_t xcd_remap;   // 1: give each XCD a contiguous span of the work list
   const double *src;   // state the fluxes are computed from (Un or U1)
   const double *un;    // Un (stage 2 only)
   double *dst;         // U1 (stage 1) or Un+1 (stage 2, may alias un)

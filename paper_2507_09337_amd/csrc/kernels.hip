@@ -345,10 +345,10 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   const double *__restrict__ own = src + boff + cidx;
 
   // stage the x/y guard ring and this thread's cell of plane z into LDS
-  auto stage_plane = [&](int z, const double (&Wc)[5]) {
+  auto stage_plane = [&](int z, const T (&Wc)[5]) {
     if (active) {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) Wp[v * PP + (tj + 2) * PX + (ti + 2)] = (T)Wc[v];
+      for (int v = 0; v < NVAR; ++v) Wp[v * PP + (tj + 2) * PX + (ti + 2)] = Wc[v];
     }
     if (gslot >= 0) {
       double Wg[5];
@@ -400,7 +400,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   // RK stage update of this thread's cell in plane z:
   //   dU = sum over x, y, z of (dt/dx_d)(F_lo - F_hi), FP64, no contraction;
   //   stage 1: U1 = Un + dU;  stage 2: Un+1 = Un/2 + (U1 + dU)/2.
-  auto update = [&](int z, const T (&fzlo)[5], const T (&fzhi)[5]) {
+  auto update = [&](int z, const double (&Us)[5], const T (&fzlo)[5], const T (&fzhi)[5]) {
 #pragma clang fp contract(off)
     if (!active) return;
     const int64_t c = (int64_t)z * plane;
@@ -414,7 +414,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       double dU = dtdx * (fxl - fxh);
       dU += dtdy * (fyl - fyh);
       if (DIM == 3) dU += dtdz * ((double)fzlo[v] - (double)fzhi[v]);
-      const double s = own[v * own_vs + c];
+      const double s = Us[v];
       if (STAGE == 1) {
         Unew[v] = s + dU;
       } else {
@@ -434,26 +434,46 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     }
   };
 
-  if (DIM == 2) {
-    double Wc[5] = {1, 0, 0, 0, 1};
-    if (active && !load_prim<MIXED>(own, own_vs, gm1, Wc)) {
+  // load the conserved state of one cell and its primitives (rounded to T)
+  auto load_cell = [&](const double *p, int64_t vs, double (&U)[5], T (&W)[5]) {
+    U[0] = p[0];
+    U[1] = p[vs];
+    U[2] = p[2 * vs];
+    U[3] = p[3 * vs];
+    U[4] = p[4 * vs];
+    double Wd[5];
+    const bool ok = MIXED ? recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)
+                          : recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd);
+    if (!ok) {
       bad = 1;
       badblk = min(badblk, b);
     }
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) W[v] = (T)Wd[v];
+  };
+
+  if (DIM == 2) {
+    double U[5] = {1, 0, 0, 0, 1};
+    T Wc[5] = {1, 0, 0, 0, 1};
+    if (active) load_cell(own, own_vs, U, Wc);
     stage_plane(0, Wc);
     __syncthreads();
     plane_faces();
     __syncthreads();
     const T zero[5] = {0, 0, 0, 0, 0};
-    update(0, zero, zero);
+    update(0, U, zero, zero);
     return;
   }
 
-  // ---- 3D: z march with a four-plane register window
-  // window (wa, wb, wc) = planes (j-1, j, j+1); iteration j loads wd = plane j+2
-  // and computes the z face j+1/2 at a single site for every face of the column.
-  double Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
-  auto load_z = [&](int z, double (&W)[5]) {
+  // ---- 3D: z march with a four-plane register window of primitives (in the
+  // flux precision) and a three-plane ring of the conserved source values
+  // (FP64), so no source cell is read twice.  At iteration j the window holds
+  // planes (j-1, j, j+1) and loads j+2; the z face j+1/2 is computed at a
+  // single site for every face of the column (the prologue iteration j = z0-1
+  // yields the face z0-1/2).
+  T Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
+  double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};  // planes j, j+1, j+2
+  auto load_z = [&](int z, T (&W)[5], double (&U)[5]) {
     if (!active) return;
     int64_t off, vs;
     if (z >= 0 && z < nz) {
@@ -462,22 +482,19 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     } else {
       cell_addr(Bp, x, y, z, off, vs);
     }
-    if (!load_prim<MIXED>(src + off, vs, gm1, W)) {
-      bad = 1;
-      badblk = min(badblk, b);
-    }
+    load_cell(src + off, vs, U, W);
   };
-  load_z(z0 - 2, Wa);
-  load_z(z0 - 1, Wb);
-  load_z(z0, Wc);
+  load_z(z0 - 2, Wa, Ud);
+  load_z(z0 - 1, Wb, Ub);
+  load_z(z0, Wc, Uc);
   T fzlo[5] = {0, 0, 0, 0, 0};
   for (int j = z0 - 1; j < z1; ++j) {
-    load_z(j + 2, Wd);
+    load_z(j + 2, Wd, Ud);
     T fz[5];
     {
       T wl[5], wr[5];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) plm((T)Wa[v], (T)Wb[v], (T)Wc[v], (T)Wd[v], wl[v], wr[v]);
+      for (int v = 0; v < NVAR; ++v) plm(Wa[v], Wb[v], Wc[v], Wd[v], wl[v], wr[v]);
       const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
       const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
       T Fr[5];
@@ -493,7 +510,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       __syncthreads();
       plane_faces();
       __syncthreads();
-      update(j, fzlo, fz);
+      update(j, Ub, fzlo, fz);
     }
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
@@ -501,6 +518,8 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       Wa[v] = Wb[v];
       Wb[v] = Wc[v];
       Wc[v] = Wd[v];
+      Ub[v] = Uc[v];
+      Uc[v] = Ud[v];
     }
   }
 }
@@ -524,6 +543,16 @@ __device__ __forceinline__ void flush_acc(DevTime *acc, double lam, int bad, int
   }
 }
 
+// Workgroups of a dispatch are handed to the 8 XCDs round-robin (workgroup i
+// runs on XCD i mod 8), and each XCD has its own L2.  Renumbering so that XCD
+// x runs the x-th contiguous span of workgroup indices keeps neighbouring
+// blocks (whose interiors are each other's guards) on one L2.  The map is a
+// bijection of [0, g) for any g.
+__device__ __forceinline__ int xcd_logical(int bid, int g) {
+  const int q = g >> 3, r = g & 7, x = bid & 7, l = bid >> 3;
+  return x * q + min(x, r) + l;
+}
+
 template <int KMASK, bool MIXED>
 constexpr size_t stage_lds_bytes() {
   using T = typename std::conditional<MIXED, float, double>::type;
@@ -544,7 +573,8 @@ __global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
   const double dt = A.dt_dev ? A.dt_dev->dt : A.dt;
   double lam = 0.0;
   int bad = 0, badblk = INT_MAX;
-  for (int i = blockIdx.x; i < A.nitems; i += gridDim.x) {
+  const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+  for (int i = first; i < A.nitems; i += gridDim.x) {
     const WorkItem *it = A.items + i;
     if ((KMASK & 1) && it->kind == KIND_T16)
       run_tile<16, 16, 1, DIM, MIXED, STAGE>(A, it, lds, dt, lam, bad, badblk);
@@ -565,7 +595,8 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
   double lam = 0.0;
   int bad = 0, badblk = INT_MAX;
   const double gm1 = A.gamma - 1.0;
-  for (int i = blockIdx.x; i < A.nitems; i += gridDim.x) {
+  const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+  for (int i = first; i < A.nitems; i += gridDim.x) {
     const WorkItem *it = A.items + i;
     const bool t16 = (KMASK & 1) && it->kind == KIND_T16;
     const int TX = t16 ? 16 : 8, NT = t16 ? 256 : 64;

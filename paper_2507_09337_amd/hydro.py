@@ -72,7 +72,7 @@ def lib():
             "hydro_batch_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
             "hydro_batch_destroy": [vp],
             "hydro_batch_set_tiling": [vp, i32, i32, i32],
-            "hydro_batch_set_grid": [vp, i32],
+            "hydro_batch_set_launch": [vp, i32, i32],
             "hydro_batch_autotune": [vp, dbl, i32],
             "hydro_batch_get_config": [vp, C.POINTER(C.c_int32), i32, C.POINTER(C.c_int32)],
             "hydro_batch_time_kernels": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
@@ -216,19 +216,19 @@ class Batch:
     def set_tiling(self, edge: int, tile: int, zchunk: int = 0):
         _check(lib().hydro_batch_set_tiling(self.h, int(edge), int(tile), int(zchunk)), "hydro_batch_set_tiling")
 
-    def set_grid(self, grid: int):
-        _check(lib().hydro_batch_set_grid(self.h, int(grid)), "hydro_batch_set_grid")
+    def set_launch(self, grid: int, xcd_remap: int = 1):
+        _check(lib().hydro_batch_set_launch(self.h, int(grid), int(xcd_remap)), "hydro_batch_set_launch")
 
     def autotune(self, gamma: float, reps: int = 3):
         _check(lib().hydro_batch_autotune(self.h, float(gamma), int(reps)), "hydro_batch_autotune")
 
     def config(self) -> dict:
-        buf = (C.c_int32 * (1 + 4 * 16))()
+        buf = (C.c_int32 * (2 + 4 * 16))()
         n = C.c_int32(0)
         _check(lib().hydro_batch_get_config(self.h, buf, 16, C.byref(n)), "hydro_batch_get_config")
-        classes = [{"edge": buf[1 + 4 * k], "tile": buf[2 + 4 * k], "zchunk": buf[3 + 4 * k], "cells": buf[4 + 4 * k]}
+        classes = [{"edge": buf[2 + 4 * k], "tile": buf[3 + 4 * k], "zchunk": buf[4 + 4 * k], "cells": buf[5 + 4 * k]}
                    for k in range(min(n.value, 16))]
-        return {"grid": buf[0], "classes": classes}
+        return {"grid": buf[0], "xcd_remap": buf[1], "classes": classes}
 
     def close(self):
         if self.h:
