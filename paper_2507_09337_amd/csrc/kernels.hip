@@ -265,6 +265,79 @@ constexpr size_t tile_lds_bytes() {
   return (size_t)NSUB * TileGeom<TX, TY>::ELEMS * sizeof(T);
 }
 
+// Per-thread geometry of one tile of a work item: the block, the thread's
+// column, dt/dx, and the guard cell this thread gathers for every plane.
+struct TileCtx {
+  int b;
+  bool active;
+  const DevBlock *Bp;
+  int x, y, z0, z1, nz, ncell;
+  double dtdx, dtdy, dtdz, dx0, dx1, dx2;
+  int64_t plane, boff, cidx;
+  int gslot;                 // LDS slot (in a [PY][PX] plane) of this thread's guard cell, -1: none
+  int64_t goff, gvs, gps;    // guard source: offset at z = 0, variable stride, z-plane stride
+};
+
+// Threads [0, 4TY) gather the x guards (side, layer, row), threads
+// [4TY, 4TY+4TX) the y guards; the assignment is fixed for the whole column.
+template <int TX, int TY, int DIM>
+__device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const WorkItem *__restrict__ it, int sub,
+                                           int lt, double dt, int PX) {
+  const int ti = lt % TX, tj = lt / TX;
+  C.b = __builtin_amdgcn_readfirstlane(it->block[sub]);  // uniform across the tile's waves
+  C.active = C.b >= 0;
+  C.Bp = A.blocks + (C.active ? C.b : 0);
+  const int x0 = C.active ? __builtin_amdgcn_readfirstlane(it->x0[sub]) : 0;
+  const int y0 = C.active ? __builtin_amdgcn_readfirstlane(it->y0[sub]) : 0;
+  C.x = x0 + ti;
+  C.y = y0 + tj;
+  C.z0 = it->z0;
+  C.z1 = it->z1;
+  C.dtdx = C.dtdy = C.dtdz = 0.0;
+  C.dx0 = C.dx1 = C.dx2 = 1.0;
+  int nx = 1, ny = 1;
+  C.nz = 1;
+  C.ncell = 1;
+  C.plane = 1;
+  C.boff = 0;
+  if (C.active) {
+    nx = C.Bp->n[0];
+    ny = C.Bp->n[1];
+    C.nz = C.Bp->n[2];
+    C.ncell = C.Bp->ncell;
+    C.boff = C.Bp->off;
+    C.plane = (int64_t)nx * ny;
+    C.dx0 = C.Bp->dx[0];
+    C.dx1 = C.Bp->dx[1];
+    C.dx2 = C.Bp->dx[2];
+    C.dtdx = dt / C.dx0;
+    C.dtdy = dt / C.dx1;
+    if (DIM == 3) C.dtdz = dt / C.dx2;
+  }
+  C.cidx = (int64_t)C.y * nx + C.x;
+  C.gslot = -1;
+  C.goff = C.gvs = C.gps = 0;
+  if (C.active && lt < 4 * (TX + TY)) {
+    int gx, gy;
+    if (lt < 4 * TY) {
+      const int side = lt / (2 * TY), r = lt % (2 * TY), layer = r / TY + 1, row = r % TY;
+      gx = side ? TX + layer - 1 : -layer;
+      gy = row;
+    } else {
+      const int l2 = lt - 4 * TY;
+      const int side = l2 / (2 * TX), r = l2 % (2 * TX), layer = r / TX + 1, col = r % TX;
+      gx = col;
+      gy = side ? TY + layer - 1 : -layer;
+    }
+    C.gslot = (gy + 2) * PX + (gx + 2);
+    const int X = x0 + gx, Y = y0 + gy;
+    cell_addr(C.Bp, X, Y, 0, C.goff, C.gvs);
+    int64_t o1, v1;
+    cell_addr(C.Bp, X, Y, DIM == 3 ? 1 : 0, o1, v1);
+    C.gps = o1 - C.goff;  // the source block's z-plane stride (same block for every z)
+  }
+}
+
 // ------------------------------------------------------------------------
 // One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
 // marched over z planes [z0, z1).
@@ -287,58 +360,18 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   T *Fx = Wp + NVAR * PP;                                // [5][TY][TX+1]
   T *Fy = Fx + NVAR * NXF;                               // [5][TY+1][TX]
 
-  // one block per tile; uniform across the tile's waves
-  const int b = __builtin_amdgcn_readfirstlane(it->block[sub]);
-  const bool active = b >= 0;
-  const DevBlock *__restrict__ Bp = A.blocks + (active ? b : 0);
-  const int x0 = active ? __builtin_amdgcn_readfirstlane(it->x0[sub]) : 0;
-  const int y0 = active ? __builtin_amdgcn_readfirstlane(it->y0[sub]) : 0;
-  const int x = x0 + ti, y = y0 + tj;
-  const int z0 = it->z0, z1 = it->z1;
+  TileCtx C;
+  tile_setup<TX, TY, DIM>(C, A, it, sub, lt, dt, PX);
+  const int b = C.b;
+  const bool active = C.active;
+  const DevBlock *__restrict__ Bp = C.Bp;
+  const int x = C.x, y = C.y, z0 = C.z0, z1 = C.z1;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
-
-  double dtdx = 0, dtdy = 0, dtdz = 0, dx0 = 1, dx1 = 1, dx2 = 1;
-  int nx = 1, ny = 1, nz = 1, ncell = 1;
-  int64_t plane = 1, boff = 0;
-  if (active) {
-    nx = Bp->n[0];
-    ny = Bp->n[1];
-    nz = Bp->n[2];
-    ncell = Bp->ncell;
-    boff = Bp->off;
-    plane = (int64_t)nx * ny;
-    dx0 = Bp->dx[0];
-    dx1 = Bp->dx[1];
-    dx2 = Bp->dx[2];
-    dtdx = dt / dx0;
-    dtdy = dt / dx1;
-    if (DIM == 3) dtdz = dt / dx2;
-  }
-  const int64_t cidx = (int64_t)y * nx + x;
-
-  // ---- guard ring assignment of this thread (fixed for the whole column)
-  // threads [0, 4TY): x guards (side, layer, row); [4TY, 4TY+4TX): y guards.
-  int gslot = -1;        // LDS index of the guard cell this thread fills
-  int64_t goff = 0, gvs = 0, gps = 0;  // source offset at z = 0, variable stride, z-plane stride
-  if (active && lt < 4 * (TX + TY)) {
-    int gx, gy;
-    if (lt < 4 * TY) {
-      const int side = lt / (2 * TY), r = lt % (2 * TY), layer = r / TY + 1, row = r % TY;
-      gx = side ? TX + layer - 1 : -layer;
-      gy = row;
-    } else {
-      const int l2 = lt - 4 * TY;
-      const int side = l2 / (2 * TX), r = l2 % (2 * TX), layer = r / TX + 1, col = r % TX;
-      gx = col;
-      gy = side ? TY + layer - 1 : -layer;
-    }
-    gslot = (gy + 2) * PX + (gx + 2);
-    const int X = x0 + gx, Y = y0 + gy;
-    cell_addr(Bp, X, Y, 0, goff, gvs);
-    int64_t o1, v1;
-    cell_addr(Bp, X, Y, DIM == 3 ? 1 : 0, o1, v1);
-    gps = o1 - goff;  // the source block's z-plane stride (same block for every z)
-  }
+  const double dtdx = C.dtdx, dtdy = C.dtdy, dtdz = C.dtdz, dx0 = C.dx0, dx1 = C.dx1, dx2 = C.dx2;
+  const int nz = C.nz, ncell = C.ncell;
+  const int64_t plane = C.plane, boff = C.boff, cidx = C.cidx;
+  const int gslot = C.gslot;
+  const int64_t goff = C.goff, gvs = C.gvs, gps = C.gps;
 
   const double *__restrict__ src = A.src;
   const int64_t own_vs = ncell;
@@ -525,6 +558,292 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
 }
 
 // ------------------------------------------------------------------------
+// Mixed-precision tile (FP32 PLM + HLLC): every minmod slope is computed once
+// per cell and direction, not once per face side.
+//
+// Per z plane j:  A) stage the plane's primitives and x/y guard ring in LDS;
+// B) each cell (and the guard cells next to the tile) forms its limited x and
+// y slopes and writes its two face states per direction; C) each face job
+// reads the two states of its face and runs HLLC; D) update.  The z slope is
+// carried down the column in registers (one minmod per cell per plane).
+// Face states at cell i along an axis: plus = W_i + D_i/2 (left state of face
+// i+1/2), minus = W_i - D_i/2 (right state of face i-1/2), D_i =
+// minmod(W_i - W_{i-1}, W_{i+1} - W_i).
+// ------------------------------------------------------------------------
+
+// minmod by sign test: min(|a|, |b|) with the sign of a when a and b share a
+// strict sign, else 0 (the branch form's value; a zero result may carry a sign).
+__device__ __forceinline__ float minmod_f(float a, float b) {
+  const float m = __builtin_copysignf(fminf(fabsf(a), fabsf(b)), a);
+  return ((__float_as_int(a) ^ __float_as_int(b)) < 0) ? 0.0f : m;
+}
+
+template <int TX>
+struct SplitGeom {
+  static constexpr int NT = TX * TX;
+  static constexpr int PX = TX + 4;
+  static constexpr int PP = PX * PX;        // primitives with the x/y guard ring (corners unused)
+  static constexpr int SC = TX + 2;         // face-state cells along the swept axis: -1 .. TX
+  static constexpr int S = TX * SC;         // face states per variable, one direction and side
+  static constexpr int NF = (TX + 1) * TX;  // faces per variable and direction
+  static constexpr int OW = 0;
+  static constexpr int OXP = OW + NVAR * PP;  // x plus states  [5][TX rows][SC]
+  static constexpr int OXM = OXP + NVAR * S;  // x minus states [5][TX rows][SC]
+  static constexpr int OYP = OXM + NVAR * S;  // y plus states  [5][SC rows][TX]
+  static constexpr int OYM = OYP + NVAR * S;  // y minus states [5][SC rows][TX]
+  static constexpr int OFX = OYM + NVAR * S;  // x fluxes [5][TX][TX+1]
+  static constexpr int OFY = OFX + NVAR * NF; // y fluxes [5][TX+1][TX]
+  static constexpr int ELEMS = OFY + NVAR * NF;
+  static constexpr int NJOB = (2 * NF + NT - 1) / NT;  // face jobs per thread per plane
+};
+
+template <int TX, int NSUB, int DIM, int STAGE>
+__device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
+                                               double dt, double &lam, int &bad, int &badblk) {
+  using G = SplitGeom<TX>;
+  constexpr int NT = G::NT, PX = G::PX, PP = G::PP, SC = G::SC, S = G::S, NF = G::NF;
+  static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
+  static_assert(8 * TX <= NT, "guard ring must fit the tile's threads");
+
+  const int tid = threadIdx.x;
+  const int sub = (NSUB == 1) ? 0 : __builtin_amdgcn_readfirstlane(tid / NT);
+  const int lt = tid - sub * NT;
+  const int ti = lt % TX, tj = lt / TX;
+  float *L = reinterpret_cast<float *>(lds) + sub * G::ELEMS;
+
+  TileCtx C;
+  tile_setup<TX, TX, DIM>(C, A, it, sub, lt, dt, PX);
+  const bool active = C.active;
+  const double gamma = A.gamma, gm1 = gamma - 1.0;
+  const float g32 = (float)gamma, rgm1 = (float)(1.0 / gm1);
+  const double *__restrict__ src = A.src;
+
+  // face jobs of this thread, the same for every plane
+  int jl[G::NJOB], jr[G::NJOB], jo[G::NJOB];
+  bool jx[G::NJOB];
+#pragma unroll
+  for (int k = 0; k < G::NJOB; ++k) {
+    const int f = lt + k * NT;
+    jx[k] = f < NF;
+    if (f < NF) {  // x face `col` of row `row`: cells col-1 | col
+      const int row = f / (TX + 1), col = f % (TX + 1);
+      jl[k] = G::OXP + row * SC + col;
+      jr[k] = G::OXM + row * SC + col + 1;
+      jo[k] = G::OFX + row * (TX + 1) + col;
+    } else if (f < 2 * NF) {  // y face `row` of column `col`: cells row-1 | row
+      const int g = f - NF, row = g / TX, col = g % TX;
+      jl[k] = G::OYP + row * TX + col;
+      jr[k] = G::OYM + (row + 1) * TX + col;
+      jo[k] = G::OFY + row * TX + col;
+    } else {
+      jl[k] = jr[k] = jo[k] = -1;
+    }
+  }
+
+  auto load_cell = [&](const double *p, int64_t vs, double (&U)[5], float (&W)[5], bool own) {
+    U[0] = p[0];
+    U[1] = p[vs];
+    U[2] = p[2 * vs];
+    U[3] = p[3 * vs];
+    U[4] = p[4 * vs];
+    double Wd[5];
+    if (!recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
+      bad = 1;
+      if (own) badblk = min(badblk, C.b);
+    }
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) W[v] = (float)Wd[v];
+  };
+
+  // A) this thread's cell and guard cell of plane z into LDS
+  auto stage_plane = [&](int z, const float (&Wc)[5]) {
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + (tj + 2) * PX + (ti + 2)] = Wc[v];
+    }
+    if (C.gslot >= 0) {
+      double Ug[5];
+      float Wg[5];
+      load_cell(src + C.goff + (int64_t)z * C.gps, C.gvs, Ug, Wg, false);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + C.gslot] = Wg[v];
+    }
+  };
+
+  // B) limited slopes and face states, x and y, of this thread's cell and of
+  // one guard cell beside the tile (threads < 4 TX)
+  auto slopes = [&](const float (&Wc)[5]) {
+    const int c = (tj + 2) * PX + (ti + 2);
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      const float *w = L + G::OW + v * PP;
+      const float wc = Wc[v];
+      const float mx = minmod_f(wc - w[c - 1], w[c + 1] - wc);
+      const float my = minmod_f(wc - w[c - PX], w[c + PX] - wc);
+      L[G::OXP + v * S + tj * SC + ti + 1] = wc + 0.5f * mx;
+      L[G::OXM + v * S + tj * SC + ti + 1] = wc - 0.5f * mx;
+      L[G::OYP + v * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
+      L[G::OYM + v * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
+    }
+    if (lt < 4 * TX) {
+      const bool xs = lt < 2 * TX;
+      const int l2 = xs ? lt : lt - 2 * TX;
+      const int side = l2 / TX, k = l2 % TX, e = side ? TX : -1;
+      // x: cell (e, row k), neighbours along x; y: cell (col k, e), along y
+      const int cc = xs ? (k + 2) * PX + (e + 2) : (e + 2) * PX + (k + 2);
+      const int st = xs ? 1 : PX;
+      const int so = xs ? k * SC + e + 1 : (e + 1) * TX + k;
+      const int op = xs ? G::OXP : G::OYP, om = xs ? G::OXM : G::OYM;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const float *w = L + G::OW + v * PP;
+        const float wc = w[cc];
+        const float m = minmod_f(wc - w[cc - st], w[cc + st] - wc);
+        L[op + v * S + so] = wc + 0.5f * m;
+        L[om + v * S + so] = wc - 0.5f * m;
+      }
+    }
+  };
+
+  // C) HLLC on every x and y face of the plane
+  auto faces = [&]() {
+#pragma unroll
+    for (int k = 0; k < G::NJOB; ++k) {
+      if (jl[k] < 0) continue;
+      const int vsS = S, vsF = NF;
+      float a[5], r[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        a[v] = L[jl[k] + v * vsS];
+        r[v] = L[jr[k] + v * vsS];
+      }
+      const bool isx = jx[k];
+      const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
+      const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
+      float F[5];
+      hllc<float>(Lr, Rr, g32, rgm1, F);
+      float *o = L + jo[k];
+      o[0] = F[0];
+      o[vsF] = isx ? F[1] : F[2];
+      o[2 * vsF] = isx ? F[2] : F[1];
+      o[3 * vsF] = F[3];
+      o[4 * vsF] = F[4];
+    }
+  };
+
+  // D) FP64 update of this thread's cell in plane z (FP32 fluxes widened)
+  auto update = [&](int z, const double (&Us)[5], const float (&fzlo)[5], const float (&fzhi)[5]) {
+    if (!active) return;
+    const int64_t c = (int64_t)z * C.plane + C.cidx;
+    double Unew[5];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      const float *fx = L + G::OFX + v * NF + tj * (TX + 1) + ti;
+      const float *fy = L + G::OFY + v * NF + tj * TX + ti;
+      double dU = C.dtdx * ((double)fx[0] - (double)fx[1]);
+      dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
+      if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
+      if (STAGE == 1) {
+        Unew[v] = Us[v] + dU;
+      } else {
+        const double un = A.un[C.boff + v * (int64_t)C.ncell + c];
+        Unew[v] = 0.5 * un + 0.5 * (Us[v] + dU);
+      }
+      A.dst[C.boff + v * (int64_t)C.ncell + c] = Unew[v];
+    }
+    if (STAGE == 2) {  // CFL rate of the new state (FP64)
+      double W[5];
+      if (!recover(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
+        bad = 1;
+        badblk = min(badblk, C.b);
+      } else {
+        lam = fmax(lam, cell_rate<DIM>(W, gamma, C.dx0, C.dx1, C.dx2));
+      }
+    }
+  };
+
+  auto plane_work = [&](int z, const float (&Wc)[5], const double (&Us)[5], const float (&fzlo)[5],
+                        const float (&fzhi)[5]) {
+    stage_plane(z, Wc);
+    __syncthreads();
+    slopes(Wc);
+    __syncthreads();
+    faces();
+    __syncthreads();
+    update(z, Us, fzlo, fzhi);
+  };
+
+  if (DIM == 2) {
+    double U[5] = {1, 0, 0, 0, 1};
+    float Wc[5] = {1, 0, 0, 0, 1};
+    if (active) load_cell(src + C.boff + C.cidx, C.ncell, U, Wc, true);
+    const float zero[5] = {0, 0, 0, 0, 0};
+    plane_work(0, Wc, U, zero, zero);
+    return;
+  }
+
+  // 3D: window Wb, Wc, Wd = planes j, j+1, j+2; carried z data: zp = plus
+  // state of plane j, dlo = W_{j+1} - W_j; ring Ub, Uc, Ud of conserved values.
+  float Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
+  double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};
+  auto load_z = [&](int z, float (&W)[5], double (&U)[5]) {
+    if (!active) return;
+    int64_t off, vs;
+    if (z >= 0 && z < C.nz) {
+      off = C.boff + (int64_t)z * C.plane + C.cidx;
+      vs = C.ncell;
+    } else {
+      cell_addr(C.Bp, C.x, C.y, z, off, vs);
+    }
+    load_cell(src + off, vs, U, W, true);
+  };
+  load_z(C.z0 - 2, Wa, Ud);
+  load_z(C.z0 - 1, Wb, Ub);
+  load_z(C.z0, Wc, Uc);
+  float zp[5], dlo[5];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) {
+    dlo[v] = Wc[v] - Wb[v];
+    zp[v] = Wb[v] + 0.5f * minmod_f(Wb[v] - Wa[v], dlo[v]);
+  }
+  float fzlo[5] = {0, 0, 0, 0, 0};
+  for (int j = C.z0 - 1; j < C.z1; ++j) {
+    load_z(j + 2, Wd, Ud);
+    float fz[5];
+    {
+      float zr[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const float dhi = Wd[v] - Wc[v];
+        const float m = minmod_f(dlo[v], dhi);
+        zr[v] = Wc[v] - 0.5f * m;
+        dlo[v] = dhi;
+        Wa[v] = Wc[v] + 0.5f * m;  // plus state of plane j+1, carried into zp below
+      }
+      const float Lr[5] = {zp[0], zp[3], zp[2], zp[1], zp[4]};
+      const float Rr[5] = {zr[0], zr[3], zr[2], zr[1], zr[4]};
+      float F[5];
+      hllc<float>(Lr, Rr, g32, rgm1, F);
+      fz[0] = F[0];
+      fz[1] = F[3];
+      fz[2] = F[2];
+      fz[3] = F[1];
+      fz[4] = F[4];
+    }
+    if (j >= C.z0) plane_work(j, Wb, Ub, fzlo, fz);
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      zp[v] = Wa[v];
+      fzlo[v] = fz[v];
+      Wb[v] = Wc[v];
+      Wc[v] = Wd[v];
+      Ub[v] = Uc[v];
+      Uc[v] = Ud[v];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
 // Wave/workgroup reductions into the accumulator.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ void flush_acc(DevTime *acc, double lam, int bad, int badblk, bool with_lam) {
@@ -556,8 +875,8 @@ __device__ __forceinline__ int xcd_logical(int bid, int g) {
 template <int KMASK, bool MIXED>
 constexpr size_t stage_lds_bytes() {
   using T = typename std::conditional<MIXED, float, double>::type;
-  constexpr size_t a = (KMASK & 1) ? tile_lds_bytes<16, 16, 1, T>() : 0;
-  constexpr size_t b = (KMASK & 2) ? tile_lds_bytes<8, 8, 4, T>() : 0;
+  constexpr size_t a = (KMASK & 1) ? (MIXED ? SplitGeom<16>::ELEMS * sizeof(float) : tile_lds_bytes<16, 16, 1, T>()) : 0;
+  constexpr size_t b = (KMASK & 2) ? (MIXED ? 4 * SplitGeom<8>::ELEMS * sizeof(float) : tile_lds_bytes<8, 8, 4, T>()) : 0;
   return a > b ? a : b;
 }
 
@@ -576,10 +895,17 @@ __global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
   const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
   for (int i = first; i < A.nitems; i += gridDim.x) {
     const WorkItem *it = A.items + i;
-    if ((KMASK & 1) && it->kind == KIND_T16)
-      run_tile<16, 16, 1, DIM, MIXED, STAGE>(A, it, lds, dt, lam, bad, badblk);
-    else if (KMASK & 2)
-      run_tile<8, 8, 4, DIM, MIXED, STAGE>(A, it, lds, dt, lam, bad, badblk);
+    if constexpr (MIXED) {
+      if ((KMASK & 1) && it->kind == KIND_T16)
+        run_tile_mixed<16, 1, DIM, STAGE>(A, it, lds, dt, lam, bad, badblk);
+      else if (KMASK & 2)
+        run_tile_mixed<8, 4, DIM, STAGE>(A, it, lds, dt, lam, bad, badblk);
+    } else {
+      if ((KMASK & 1) && it->kind == KIND_T16)
+        run_tile<16, 16, 1, DIM, false, STAGE>(A, it, lds, dt, lam, bad, badblk);
+      else if (KMASK & 2)
+        run_tile<8, 8, 4, DIM, false, STAGE>(A, it, lds, dt, lam, bad, badblk);
+    }
     __syncthreads();  // LDS is reused by the next item
   }
   // Stage 1 reports nothing: a bad Un was already reported by the rate
