@@ -69,8 +69,9 @@ def sample_blocks(P, k=6):
     return sorted(ids)
 
 
-def one_step_errors(P, arena, U0_dev, mesh, packets_fp64, packets_mixed):
-    """Error of one step from the initial state vs the oracle on sampled blocks."""
+def one_step_errors(P, arena, U0_dev, packets_fp64, packets_mixed):
+    """Error of one step from the initial state vs the oracle on sampled blocks
+    (used for workloads without a centred subset)."""
     import torch
 
     from oracle import oracle as O
@@ -81,7 +82,7 @@ def one_step_errors(P, arena, U0_dev, mesh, packets_fp64, packets_mixed):
     ids = sample_blocks(P)
     dt = O.dt(P.mesh, P.U0, P.gamma, P.cfl)
     ref = O.step_subset(P.mesh, P.U0, dt, P.gamma, ids)
-    out = {}
+    out = {"kind": "one step from the initial state, sampled blocks", "sample_blocks": len(ids)}
     for name, pks in (("fp64", packets_fp64), ("mixed", packets_mixed)):
         arena.copy_(U0_dev)
         b = H.Batch(pks)
@@ -93,8 +94,59 @@ def one_step_errors(P, arena, U0_dev, mesh, packets_fp64, packets_mixed):
             o, n = int(P.mesh.offset[i]), 5 * int(P.mesh.ncells[i])
             U[o:o + n] = arena[o:o + n].cpu().numpy()
         out[name] = {"max_rel_err": rel_err(P.mesh, U, ref, ids), "l1_rho_rel": l1_rho(P.mesh, U, ref, ids)}
-    out["sample_blocks"] = len(ids)
     return out
+
+
+def region_around(P, steps):
+    """Block ids of the centred subset grown by the domain of dependence of
+    `steps` SSP-RK2 steps (two guard cells per stage, four cells per step),
+    or None when that covers the whole mesh."""
+    sub = P.meta.get("subset")
+    if sub is None or P.mesh.grid is None:
+        return None
+    n = int(P.mesh.n[0, 0])
+    margin = -(-4 * steps // n)
+    nbx, nby, nbz = P.mesh.grid
+    width = round(len(sub) ** (1 / 3))
+    lo = [(d - width) // 2 - margin for d in (nbx, nby, nbz)]
+    hi = [(d - width) // 2 + width + margin for d in (nbx, nby, nbz)]
+    if any(l < 0 for l in lo) or any(h > d for h, d in zip(hi, (nbx, nby, nbz))):
+        return None
+    return np.asarray([(z * nby + y) * nbx + x for z in range(lo[2], hi[2]) for y in range(lo[1], hi[1])
+                       for x in range(lo[0], hi[0])], dtype=np.int64)
+
+
+def oracle_region_run(P, steps):
+    """The oracle, as it stands, on the region around the centred subset for
+    `steps` steps (dt from the region each step: the blast, which sets the
+    global maximum rate, lies inside it).  Returns (region ids, state of the
+    region, cpu timing dict)."""
+    from oracle import oracle as O
+
+    ids = region_around(P, steps)
+    m = P.mesh.subset(ids)
+    U = P.mesh.gather(P.U0, ids)
+    t0 = time.perf_counter()
+    dts, _ = O.run(m, U, steps, P.cfl, P.gamma)
+    el = time.perf_counter() - t0
+    cells = m.total_cells
+    cpu = {"value": cells * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+           "sample": f"{len(ids)} blocks ({cells} cells) around the centred {len(P.meta['subset'])}-block subset "
+                     f"of the same workload, {steps} steps, {el:.1f} s"}
+    return ids, m, U, dts, cpu
+
+
+def subset_errors(P, ids, m, Uref, U_gpu_sub):
+    """Errors of GPU states (arrays of the subset blocks, subset layout) vs the
+    oracle's region run on the centred subset."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import l1_rho, rel_err
+
+    pos = {int(b): k for k, b in enumerate(ids)}
+    inner = [pos[int(b)] for b in P.meta["subset"]]
+    ms = m.subset(inner)
+    R = m.gather(Uref, inner)
+    return {"max_rel_err": rel_err(ms, U_gpu_sub, R), "l1_rho_rel": l1_rho(ms, U_gpu_sub, R)}
 
 
 def copy_bandwidth(n_doubles=1 << 28, reps=5):
@@ -118,27 +170,6 @@ def copy_bandwidth(n_doubles=1 << 28, reps=5):
     torch.cuda.empty_cache()
     return {"gbs": 2 * 8 * n_doubles / (ms.value * 1e-3) / 1e9, "bytes_per_copy": 16 * n_doubles, "ms": ms.value,
             "verified": ok}
-
-
-def cpu_baseline(P, budget_s=12.0):
-    """The oracle as it stands, on the 8x8x8-block cube at the centre of the
-    workload (or the first 512 blocks), steps until ~budget_s of CPU work."""
-    from oracle import oracle as O
-
-    sub = P.meta.get("subset")
-    ids = sub if sub is not None else np.arange(min(512, P.mesh.nblocks))
-    m = P.mesh.subset(ids)
-    U = P.mesh.gather(P.U0, ids)
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and steps < 50:
-        dt = O.dt(m, U, P.gamma, P.cfl)
-        O.step(m, U, dt, P.gamma)
-        steps += 1
-    el = time.perf_counter() - t0
-    cells = m.total_cells
-    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{len(ids)} blocks ({cells} cells) of the workload as their own periodic mesh, {steps} steps, "
-                      f"{el:.1f} s, dt from the sample each step"}
 
 
 def main():
@@ -179,11 +210,15 @@ def main():
     pkmx = [H.Packet(mesh, ids, H.FP32_FP64) for ids in P.packets]
     log(f"{len(P.packets)} packets")
 
-    errs = None if args.no_check else one_step_errors(P, arena, U0_dev, mesh, pk64, pkmx)
-    log("one-step errors vs oracle:", json.dumps(errs))
+    region = None if args.no_check else region_around(P, args.steps)
+    errs = None
+    if not args.no_check and region is None:
+        errs = one_step_errors(P, arena, U0_dev, pk64, pkmx)
+        log("one-step errors vs oracle:", json.dumps(errs))
 
     results = {}
     kernel_ms = {}
+    gpu_sub = {}
     for name, pks in (("batched_mixed", pkmx), ("batched_fp64", pk64)):
         arena.copy_(U0_dev)
         b = H.Batch(pks)
@@ -197,9 +232,15 @@ def main():
         el = time.perf_counter() - ts
         results[name] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                          "config": b.config()}
+        # kernel durations: `steps` eager steps from the initial state
         arena.copy_(U0_dev)
         kernel_ms[name] = b.time_kernels(args.steps, P.cfl, P.gamma)
         b.close()
+        if region is not None:  # the state after `steps` steps, centred subset blocks
+            torch.cuda.synchronize()
+            gpu_sub[name] = np.concatenate([arena[int(P.mesh.offset[i]):int(P.mesh.offset[i]) +
+                                                  5 * int(P.mesh.ncells[i])].cpu().numpy()
+                                            for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
 
     if not args.no_plain:
@@ -222,6 +263,31 @@ def main():
         b.close()
         log("plain_fp64", json.dumps(results["plain_fp64"]))
 
+    cpu = None
+    if region is not None:
+        ids, m, Uref, dts, cpu = oracle_region_run(P, args.steps)
+        errs = {"kind": f"after {args.steps} steps from the initial state, on the centred "
+                        f"{len(P.meta['subset'])}-block subset (full-size run on the GPU; oracle on the region "
+                        f"around the subset that covers its domain of dependence)"}
+        for name, key in (("batched_mixed", "mixed"), ("batched_fp64", "fp64")):
+            errs[key] = subset_errors(P, ids, m, Uref, gpu_sub[name])
+        log("subset errors vs oracle:", json.dumps(errs))
+    if cpu is None and not args.no_cpu:
+        from oracle import oracle as O
+
+        ids = np.arange(min(512, P.mesh.nblocks))
+        m = P.mesh.subset(ids)
+        U = P.mesh.gather(P.U0, ids)
+        t0, k = time.perf_counter(), 0
+        while time.perf_counter() - t0 < 12.0 and k < 50:
+            O.step(m, U, O.dt(m, U, P.gamma, P.cfl), P.gamma)
+            k += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": m.total_cells * k / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"first {len(ids)} blocks as their own mesh, {k} steps, {el:.1f} s"}
+    if cpu:
+        log("cpu_baseline", json.dumps(cpu))
+
     head = results["batched_mixed"]
     km = kernel_ms["batched_mixed"]
     stage_ms = km["stage1_ms"] + km["stage2_ms"]
@@ -236,10 +302,6 @@ def main():
     }
     km64 = kernel_ms["batched_fp64"]
     ach64 = BYTES_PER_CELL_UPDATE * cells / ((km64["stage1_ms"] + km64["stage2_ms"]) * 1e-3) / 1e9
-
-    cpu = None if args.no_cpu else cpu_baseline(P)
-    if cpu:
-        log("cpu_baseline", json.dumps(cpu))
 
     line = {
         "metric": METRIC,
@@ -263,7 +325,7 @@ def main():
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "config"} for k, v in results.items()},
         "batched_fp64_roofline_frac": ach64 / HBM_PEAK_GBS,
         "tuning": results["batched_mixed"]["config"],
-        "errors_vs_oracle_one_step": errs,
+        "errors_vs_oracle": errs,
     }
     if "plain_fp64" in results:
         line["speedup_vs_plain_fp64"] = head["cell_updates_per_s"] / results["plain_fp64"]["cell_updates_per_s"]
