@@ -640,12 +640,16 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     }
   }
 
-  auto load_cell = [&](const double *p, int64_t vs, double (&U)[5], float (&W)[5], bool own) {
-    U[0] = p[0];
-    U[1] = p[vs];
-    U[2] = p[2 * vs];
-    U[3] = p[3 * vs];
-    U[4] = p[4 * vs];
+  // Global loads are issued early and consumed late (software pipeline):
+  // at the top of the iteration for plane j the thread issues its own cell of
+  // plane j+2 (and, in stage 2, Un of plane j); right after staging plane j it
+  // issues its guard cell of plane j+1.  Their latency is covered by the LDS
+  // phases of plane j.
+  auto fetch = [&](const double *p, int64_t vs, double (&U)[5]) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) U[v] = p[v * vs];
+  };
+  auto prims = [&](const double (&U)[5], float (&W)[5], bool own) {
     double Wd[5];
     if (!recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
       bad = 1;
@@ -654,17 +658,19 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) W[v] = (float)Wd[v];
   };
+  auto fetch_guard = [&](int z, double (&G)[5]) {
+    if (C.gslot >= 0) fetch(src + C.goff + (int64_t)z * C.gps, C.gvs, G);
+  };
 
   // A) this thread's cell and guard cell of plane z into LDS
-  auto stage_plane = [&](int z, const float (&Wc)[5]) {
+  auto stage_plane = [&](const float (&Wc)[5], const double (&Gr)[5]) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + (tj + 2) * PX + (ti + 2)] = Wc[v];
     }
     if (C.gslot >= 0) {
-      double Ug[5];
       float Wg[5];
-      load_cell(src + C.goff + (int64_t)z * C.gps, C.gvs, Ug, Wg, false);
+      prims(Gr, Wg, false);
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + C.gslot] = Wg[v];
     }
@@ -731,8 +737,11 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     }
   };
 
-  // D) FP64 update of this thread's cell in plane z (FP32 fluxes widened)
-  auto update = [&](int z, const double (&Us)[5], const float (&fzlo)[5], const float (&fzhi)[5]) {
+  const double rdx0 = 1.0 / C.dx0, rdx1 = 1.0 / C.dx1, rdx2 = 1.0 / C.dx2;
+  // D) FP64 update of this thread's cell in plane z (FP32 fluxes widened);
+  // Un is the prefetched stage-2 state of the cell
+  auto update = [&](int z, const double (&Us)[5], const double (&Un)[5], const float (&fzlo)[5],
+                    const float (&fzhi)[5]) {
     if (!active) return;
     const int64_t c = (int64_t)z * C.plane + C.cidx;
     double Unew[5];
@@ -743,42 +752,42 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       double dU = C.dtdx * ((double)fx[0] - (double)fx[1]);
       dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
       if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
-      if (STAGE == 1) {
-        Unew[v] = Us[v] + dU;
-      } else {
-        const double un = A.un[C.boff + v * (int64_t)C.ncell + c];
-        Unew[v] = 0.5 * un + 0.5 * (Us[v] + dU);
-      }
+      Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
       A.dst[C.boff + v * (int64_t)C.ncell + c] = Unew[v];
     }
-    if (STAGE == 2) {  // CFL rate of the new state (FP64)
+    if (STAGE == 2) {  // CFL rate of the new state, FP64 (reciprocals instead of divisions)
       double W[5];
-      if (!recover(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
+      if (!recover_fast(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
         bad = 1;
         badblk = min(badblk, C.b);
       } else {
-        lam = fmax(lam, cell_rate<DIM>(W, gamma, C.dx0, C.dx1, C.dx2));
+        const double cs = __builtin_sqrt(gamma * W[4] / W[0]);
+        double l = (fabs(W[1]) + cs) * rdx0 + (fabs(W[2]) + cs) * rdx1;
+        if (DIM == 3) l += (fabs(W[3]) + cs) * rdx2;
+        lam = fmax(lam, l);
       }
     }
   };
+  auto fetch_un = [&](int z, double (&Un)[5]) {
+    if (STAGE == 2 && active) fetch(A.un + C.boff + (int64_t)z * C.plane + C.cidx, C.ncell, Un);
+  };
 
-  auto plane_work = [&](int z, const float (&Wc)[5], const double (&Us)[5], const float (&fzlo)[5],
-                        const float (&fzhi)[5]) {
-    stage_plane(z, Wc);
+  double Gr[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
+  if (DIM == 2) {
+    double U[5] = {1, 0, 0, 0, 1};
+    float Wc[5] = {1, 0, 0, 0, 1};
+    if (active) fetch(src + C.boff + C.cidx, C.ncell, U);
+    fetch_guard(0, Gr);
+    fetch_un(0, Un);
+    if (active) prims(U, Wc, true);
+    const float zero[5] = {0, 0, 0, 0, 0};
+    stage_plane(Wc, Gr);
     __syncthreads();
     slopes(Wc);
     __syncthreads();
     faces();
     __syncthreads();
-    update(z, Us, fzlo, fzhi);
-  };
-
-  if (DIM == 2) {
-    double U[5] = {1, 0, 0, 0, 1};
-    float Wc[5] = {1, 0, 0, 0, 1};
-    if (active) load_cell(src + C.boff + C.cidx, C.ncell, U, Wc, true);
-    const float zero[5] = {0, 0, 0, 0, 0};
-    plane_work(0, Wc, U, zero, zero);
+    update(0, U, Un, zero, zero);
     return;
   }
 
@@ -786,7 +795,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   // state of plane j, dlo = W_{j+1} - W_j; ring Ub, Uc, Ud of conserved values.
   float Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
   double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};
-  auto load_z = [&](int z, float (&W)[5], double (&U)[5]) {
+  auto fetch_z = [&](int z, double (&U)[5]) {
     if (!active) return;
     int64_t off, vs;
     if (z >= 0 && z < C.nz) {
@@ -795,11 +804,17 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     } else {
       cell_addr(C.Bp, C.x, C.y, z, off, vs);
     }
-    load_cell(src + off, vs, U, W, true);
+    fetch(src + off, vs, U);
   };
-  load_z(C.z0 - 2, Wa, Ud);
-  load_z(C.z0 - 1, Wb, Ub);
-  load_z(C.z0, Wc, Uc);
+  fetch_z(C.z0 - 2, Ud);
+  fetch_z(C.z0 - 1, Ub);
+  fetch_z(C.z0, Uc);
+  fetch_guard(C.z0, Gr);
+  if (active) {
+    prims(Ud, Wa, true);
+    prims(Ub, Wb, true);
+    prims(Uc, Wc, true);
+  }
   float zp[5], dlo[5];
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) {
@@ -808,7 +823,19 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   }
   float fzlo[5] = {0, 0, 0, 0, 0};
   for (int j = C.z0 - 1; j < C.z1; ++j) {
-    load_z(j + 2, Wd, Ud);
+    const bool work = j >= C.z0;
+    fetch_z(j + 2, Ud);
+    if (work) {
+      fetch_un(j, Un);
+      stage_plane(Wb, Gr);
+      if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
+      __syncthreads();
+      slopes(Wb);
+      __syncthreads();
+      faces();
+    }
+    // z face j+1/2 (one site for every z face of the column)
+    if (active) prims(Ud, Wd, true);
     float fz[5];
     {
       float zr[5];
@@ -830,7 +857,10 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       fz[3] = F[1];
       fz[4] = F[4];
     }
-    if (j >= C.z0) plane_work(j, Wb, Ub, fzlo, fz);
+    if (work) {
+      __syncthreads();
+      update(j, Ub, Un, fzlo, fz);
+    }
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
       zp[v] = Wa[v];
@@ -880,8 +910,10 @@ constexpr size_t stage_lds_bytes() {
   return a > b ? a : b;
 }
 
+// Occupancy target: the mixed tile's LDS (41 KiB) allows three workgroups
+// (three waves per SIMD) per CU; the register budget is capped to match.
 template <int DIM, bool MIXED, int STAGE, int KMASK>
-__global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
     // plain path: this launch precedes the stage-2 launch that accumulates
