@@ -166,11 +166,20 @@ __device__ __forceinline__ bool recover(double U0, double U1, double U2, double 
   return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
 }
 
-// Faster recovery for the mixed path (one reciprocal); its primitives are
-// rounded to FP32 right after.
+// 1/x in FP64 from the hardware reciprocal estimate refined by two Newton
+// steps (about 1 ulp for normal x; no denormal or overflow scaling).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Faster recovery for the mixed path (one refined reciprocal); its primitives
+// are rounded to FP32 right after, while rho e = E - m.u/2 keeps FP64.
 __device__ __forceinline__ bool recover_fast(double U0, double U1, double U2, double U3, double U4, double gm1,
                                              double W[5]) {
-  const double inv = 1.0 / U0;
+  const double inv = rcp_nr(U0);
   const double u = U1 * inv, v = U2 * inv, w = U3 * inv;
   const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
   const double p = gm1 * rhoe;
@@ -620,11 +629,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 
   // face jobs of this thread, the same for every plane
   int jl[G::NJOB], jr[G::NJOB], jo[G::NJOB];
-  bool jx[G::NJOB];
 #pragma unroll
   for (int k = 0; k < G::NJOB; ++k) {
     const int f = lt + k * NT;
-    jx[k] = f < NF;
     if (f < NF) {  // x face `col` of row `row`: cells col-1 | col
       const int row = f / (TX + 1), col = f % (TX + 1);
       jl[k] = G::OXP + row * SC + col;
@@ -688,8 +695,10 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       const float my = minmod_f(wc - w[c - PX], w[c + PX] - wc);
       L[G::OXP + v * S + tj * SC + ti + 1] = wc + 0.5f * mx;
       L[G::OXM + v * S + tj * SC + ti + 1] = wc - 0.5f * mx;
-      L[G::OYP + v * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
-      L[G::OYM + v * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
+      // y states are stored in the y-face frame (u and v swapped: slot 1 = normal)
+      const int vy = (v == 1) ? 2 : (v == 2) ? 1 : v;
+      L[G::OYP + vy * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
+      L[G::OYM + vy * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
     }
     if (lt < 4 * TX) {
       const bool xs = lt < 2 * TX;
@@ -705,8 +714,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
         const float *w = L + G::OW + v * PP;
         const float wc = w[cc];
         const float m = minmod_f(wc - w[cc - st], w[cc + st] - wc);
-        L[op + v * S + so] = wc + 0.5f * m;
-        L[om + v * S + so] = wc - 0.5f * m;
+        const int vs = xs ? v : (v == 1) ? 2 : (v == 2) ? 1 : v;
+        L[op + vs * S + so] = wc + 0.5f * m;
+        L[om + vs * S + so] = wc - 0.5f * m;
       }
     }
   };
@@ -723,17 +733,13 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
         a[v] = L[jl[k] + v * vsS];
         r[v] = L[jr[k] + v * vsS];
       }
-      const bool isx = jx[k];
-      const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
-      const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
+      // both directions' states are in their face frame; y fluxes stay in
+      // the y frame too (the update reads them with slots 1 and 2 swapped)
       float F[5];
-      hllc<float>(Lr, Rr, g32, rgm1, F);
+      hllc<float>(a, r, g32, rgm1, F);
       float *o = L + jo[k];
-      o[0] = F[0];
-      o[vsF] = isx ? F[1] : F[2];
-      o[2 * vsF] = isx ? F[2] : F[1];
-      o[3 * vsF] = F[3];
-      o[4 * vsF] = F[4];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) o[v * vsF] = F[v];
     }
   };
 
@@ -747,21 +753,25 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     double Unew[5];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
+      const int vy = (v == 1) ? 2 : (v == 2) ? 1 : v;  // y fluxes are in the y-face frame
       const float *fx = L + G::OFX + v * NF + tj * (TX + 1) + ti;
-      const float *fy = L + G::OFY + v * NF + tj * TX + ti;
+      const float *fy = L + G::OFY + vy * NF + tj * TX + ti;
       double dU = C.dtdx * ((double)fx[0] - (double)fx[1]);
       dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
       if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
       Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
-      A.dst[C.boff + v * (int64_t)C.ncell + c] = Unew[v];
+      (A.dst + C.boff)[(int64_t)v * C.ncell + (int)c] = Unew[v];
     }
-    if (STAGE == 2) {  // CFL rate of the new state, FP64 (reciprocals instead of divisions)
+    if (STAGE == 2) {  // CFL rate of the new state in FP64: c = g p / sqrt(g p rho), refined rsq
       double W[5];
       if (!recover_fast(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
         bad = 1;
         badblk = min(badblk, C.b);
       } else {
-        const double cs = __builtin_sqrt(gamma * W[4] / W[0]);
+        const double gp = gamma * W[4], q = gp * W[0];
+        double y = __builtin_amdgcn_rsq(q);
+        y = y * __builtin_fma(-0.5 * q * y, y, 1.5);
+        const double cs = gp * y;
         double l = (fabs(W[1]) + cs) * rdx0 + (fabs(W[2]) + cs) * rdx1;
         if (DIM == 3) l += (fabs(W[3]) + cs) * rdx2;
         lam = fmax(lam, l);
@@ -769,7 +779,12 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     }
   };
   auto fetch_un = [&](int z, double (&Un)[5]) {
-    if (STAGE == 2 && active) fetch(A.un + C.boff + (int64_t)z * C.plane + C.cidx, C.ncell, Un);
+    if (STAGE == 2 && active) {
+      const double *__restrict__ ub = A.un + C.boff;
+      const int o = z * (int)C.plane + (int)C.cidx;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Un[v] = ub[(int64_t)v * C.ncell + o];
+    }
   };
 
   double Gr[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
@@ -795,16 +810,20 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   // state of plane j, dlo = W_{j+1} - W_j; ring Ub, Uc, Ud of conserved values.
   float Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
   double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};
+  // own cells: wave-uniform base per variable, 32-bit lane offset
+  const double *__restrict__ sb = src + C.boff;
+  const int plane32 = (int)C.plane, cidx32 = (int)C.cidx;
   auto fetch_z = [&](int z, double (&U)[5]) {
     if (!active) return;
-    int64_t off, vs;
     if (z >= 0 && z < C.nz) {
-      off = C.boff + (int64_t)z * C.plane + C.cidx;
-      vs = C.ncell;
+      const int o = z * plane32 + cidx32;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) U[v] = sb[(int64_t)v * C.ncell + o];
     } else {
+      int64_t off, vs;
       cell_addr(C.Bp, C.x, C.y, z, off, vs);
+      fetch(src + off, vs, U);
     }
-    fetch(src + off, vs, U);
   };
   fetch_z(C.z0 - 2, Ud);
   fetch_z(C.z0 - 1, Ub);
@@ -910,10 +929,8 @@ constexpr size_t stage_lds_bytes() {
   return a > b ? a : b;
 }
 
-// Occupancy target: the mixed tile's LDS (41 KiB) allows three workgroups
-// (three waves per SIMD) per CU; the register budget is capped to match.
 template <int DIM, bool MIXED, int STAGE, int KMASK>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_stage(StageArgs A) {
+__global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
     // plain path: this launch precedes the stage-2 launch that accumulates
