@@ -386,17 +386,41 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   const int64_t own_vs = ncell;
   const double *__restrict__ own = src + boff + cidx;
 
-  // stage the x/y guard ring and this thread's cell of plane z into LDS
-  auto stage_plane = [&](int z, const T (&Wc)[5]) {
+  // Global loads are issued early and consumed late, as in the mixed tile:
+  // own cell of plane j+2 and (stage 2) Un of plane j at the top of the
+  // iteration for plane j, the guard cell of plane j+1 right after staging
+  // plane j.  The arithmetic and its order are unchanged by the pipeline.
+  auto fetch = [&](const double *p, int64_t vs, double (&U)[5]) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) U[v] = p[v * vs];
+  };
+  auto prims = [&](const double (&U)[5], T (&W)[5], bool own) {
+    double Wd[5];
+    if (!recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
+      bad = 1;
+      if (own) badblk = min(badblk, b);
+    }
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) W[v] = (T)Wd[v];
+  };
+  auto fetch_guard = [&](int z, double (&G)[5]) {
+    if (gslot >= 0) fetch(src + goff + (int64_t)z * gps, gvs, G);
+  };
+  auto fetch_un = [&](int z, double (&Un)[5]) {
+    if (STAGE == 2 && active) fetch(A.un + boff + (int64_t)z * plane + cidx, own_vs, Un);
+  };
+
+  // stage the x/y guard ring and this thread's cell of the plane into LDS
+  auto stage_plane = [&](const T (&Wc)[5], const double (&Gr)[5]) {
     if (active) {
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) Wp[v * PP + (tj + 2) * PX + (ti + 2)] = Wc[v];
     }
     if (gslot >= 0) {
-      double Wg[5];
-      if (!load_prim<MIXED>(src + goff + (int64_t)z * gps, gvs, gm1, Wg)) bad = 1;
+      T Wg[5];
+      prims(Gr, Wg, false);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) Wp[v * PP + gslot] = (T)Wg[v];
+      for (int v = 0; v < NVAR; ++v) Wp[v * PP + gslot] = Wg[v];
     }
   };
 
@@ -442,7 +466,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   // RK stage update of this thread's cell in plane z:
   //   dU = sum over x, y, z of (dt/dx_d)(F_lo - F_hi), FP64, no contraction;
   //   stage 1: U1 = Un + dU;  stage 2: Un+1 = Un/2 + (U1 + dU)/2.
-  auto update = [&](int z, const double (&Us)[5], const T (&fzlo)[5], const T (&fzhi)[5]) {
+  auto update = [&](int z, const double (&Us)[5], const double (&Un)[5], const T (&fzlo)[5], const T (&fzhi)[5]) {
 #pragma clang fp contract(off)
     if (!active) return;
     const int64_t c = (int64_t)z * plane;
@@ -456,13 +480,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       double dU = dtdx * (fxl - fxh);
       dU += dtdy * (fyl - fyh);
       if (DIM == 3) dU += dtdz * ((double)fzlo[v] - (double)fzhi[v]);
-      const double s = Us[v];
-      if (STAGE == 1) {
-        Unew[v] = s + dU;
-      } else {
-        const double un = A.un[boff + v * own_vs + c + cidx];
-        Unew[v] = 0.5 * un + 0.5 * (s + dU);
-      }
+      Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
       A.dst[boff + v * own_vs + c + cidx] = Unew[v];
     }
     if (STAGE == 2) {  // CFL rate of the new state (FP64)
@@ -476,46 +494,31 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     }
   };
 
-  // load the conserved state of one cell and its primitives (rounded to T)
-  auto load_cell = [&](const double *p, int64_t vs, double (&U)[5], T (&W)[5]) {
-    U[0] = p[0];
-    U[1] = p[vs];
-    U[2] = p[2 * vs];
-    U[3] = p[3 * vs];
-    U[4] = p[4 * vs];
-    double Wd[5];
-    const bool ok = MIXED ? recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)
-                          : recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd);
-    if (!ok) {
-      bad = 1;
-      badblk = min(badblk, b);
-    }
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) W[v] = (T)Wd[v];
-  };
-
+  double Gr[5] = {0, 0, 0, 0, 0}, Un[5] = {0, 0, 0, 0, 0};
   if (DIM == 2) {
     double U[5] = {1, 0, 0, 0, 1};
     T Wc[5] = {1, 0, 0, 0, 1};
-    if (active) load_cell(own, own_vs, U, Wc);
-    stage_plane(0, Wc);
+    if (active) fetch(own, own_vs, U);
+    fetch_guard(0, Gr);
+    fetch_un(0, Un);
+    if (active) prims(U, Wc, true);
+    stage_plane(Wc, Gr);
     __syncthreads();
     plane_faces();
     __syncthreads();
     const T zero[5] = {0, 0, 0, 0, 0};
-    update(0, U, zero, zero);
+    update(0, U, Un, zero, zero);
     return;
   }
 
-  // ---- 3D: z march with a four-plane register window of primitives (in the
-  // flux precision) and a three-plane ring of the conserved source values
-  // (FP64), so no source cell is read twice.  At iteration j the window holds
-  // planes (j-1, j, j+1) and loads j+2; the z face j+1/2 is computed at a
-  // single site for every face of the column (the prologue iteration j = z0-1
-  // yields the face z0-1/2).
+  // ---- 3D: z march with a four-plane register window of primitives and a
+  // three-plane ring of the conserved source values, so no source cell is
+  // read twice.  At iteration j the window holds planes (j-1, j, j+1) and
+  // receives j+2; the z face j+1/2 is computed at a single site for every
+  // face of the column (the prologue iteration j = z0-1 yields the face z0-1/2).
   T Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
   double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};  // planes j, j+1, j+2
-  auto load_z = [&](int z, T (&W)[5], double (&U)[5]) {
+  auto fetch_z = [&](int z, double (&U)[5]) {
     if (!active) return;
     int64_t off, vs;
     if (z >= 0 && z < nz) {
@@ -524,14 +527,29 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     } else {
       cell_addr(Bp, x, y, z, off, vs);
     }
-    load_cell(src + off, vs, U, W);
+    fetch(src + off, vs, U);
   };
-  load_z(z0 - 2, Wa, Ud);
-  load_z(z0 - 1, Wb, Ub);
-  load_z(z0, Wc, Uc);
+  fetch_z(z0 - 2, Ud);
+  fetch_z(z0 - 1, Ub);
+  fetch_z(z0, Uc);
+  fetch_guard(z0, Gr);
+  if (active) {
+    prims(Ud, Wa, true);
+    prims(Ub, Wb, true);
+    prims(Uc, Wc, true);
+  }
   T fzlo[5] = {0, 0, 0, 0, 0};
   for (int j = z0 - 1; j < z1; ++j) {
-    load_z(j + 2, Wd, Ud);
+    const bool work = j >= z0;
+    fetch_z(j + 2, Ud);
+    if (work) {
+      fetch_un(j, Un);
+      stage_plane(Wb, Gr);
+      if (j + 1 < z1) fetch_guard(j + 1, Gr);
+      __syncthreads();
+      plane_faces();
+    }
+    if (active) prims(Ud, Wd, true);
     T fz[5];
     {
       T wl[5], wr[5];
@@ -547,12 +565,9 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       fz[3] = Fr[1];
       fz[4] = Fr[4];
     }
-    if (j >= z0) {
-      stage_plane(j, Wb);
+    if (work) {
       __syncthreads();
-      plane_faces();
-      __syncthreads();
-      update(j, Ub, fzlo, fz);
+      update(j, Ub, Un, fzlo, fz);
     }
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
