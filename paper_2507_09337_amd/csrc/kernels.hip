@@ -644,9 +644,11 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 
   // face jobs of this thread, the same for every plane
   int jl[G::NJOB], jr[G::NJOB], jo[G::NJOB];
+  bool jx[G::NJOB];
 #pragma unroll
   for (int k = 0; k < G::NJOB; ++k) {
     const int f = lt + k * NT;
+    jx[k] = f < NF;
     if (f < NF) {  // x face `col` of row `row`: cells col-1 | col
       const int row = f / (TX + 1), col = f % (TX + 1);
       jl[k] = G::OXP + row * SC + col;
@@ -711,9 +713,8 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       L[G::OXP + v * S + tj * SC + ti + 1] = wc + 0.5f * mx;
       L[G::OXM + v * S + tj * SC + ti + 1] = wc - 0.5f * mx;
       // y states are stored in the y-face frame (u and v swapped: slot 1 = normal)
-      const int vy = (v == 1) ? 2 : (v == 2) ? 1 : v;
-      L[G::OYP + vy * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
-      L[G::OYM + vy * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
+      L[G::OYP + v * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
+      L[G::OYM + v * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
     }
     if (lt < 4 * TX) {
       const bool xs = lt < 2 * TX;
@@ -729,9 +730,8 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
         const float *w = L + G::OW + v * PP;
         const float wc = w[cc];
         const float m = minmod_f(wc - w[cc - st], w[cc + st] - wc);
-        const int vs = xs ? v : (v == 1) ? 2 : (v == 2) ? 1 : v;
-        L[op + vs * S + so] = wc + 0.5f * m;
-        L[om + vs * S + so] = wc - 0.5f * m;
+        L[op + v * S + so] = wc + 0.5f * m;
+        L[om + v * S + so] = wc - 0.5f * m;
       }
     }
   };
@@ -750,11 +750,17 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       }
       // both directions' states are in their face frame; y fluxes stay in
       // the y frame too (the update reads them with slots 1 and 2 swapped)
+      const bool isx = jx[k];
+      const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
+      const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
       float F[5];
-      hllc<float>(a, r, g32, rgm1, F);
+      hllc<float>(Lr, Rr, g32, rgm1, F);
       float *o = L + jo[k];
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) o[v * vsF] = F[v];
+      o[0] = F[0];
+      o[vsF] = isx ? F[1] : F[2];
+      o[2 * vsF] = isx ? F[2] : F[1];
+      o[3 * vsF] = F[3];
+      o[4 * vsF] = F[4];
     }
   };
 
@@ -768,9 +774,8 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     double Unew[5];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
-      const int vy = (v == 1) ? 2 : (v == 2) ? 1 : v;  // y fluxes are in the y-face frame
       const float *fx = L + G::OFX + v * NF + tj * (TX + 1) + ti;
-      const float *fy = L + G::OFY + vy * NF + tj * TX + ti;
+      const float *fy = L + G::OFY + v * NF + tj * TX + ti;
       double dU = C.dtdx * ((double)fx[0] - (double)fx[1]);
       dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
       if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
