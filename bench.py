@@ -205,6 +205,41 @@ def measured_traffic(kernel_names):
     return total
 
 
+def host_packets_bench(args):
+    """Uneven workload (self-periodic blocks, closed packets) with the state in
+    pinned host memory: every step copies each packet in and out."""
+    import torch
+
+    from paper_2507_09337_amd import hydro as H
+    from paper_2507_09337_amd import inputs as I
+
+    P = I.uneven()
+    cells = P.mesh.total_cells
+    out = {}
+    for prec, name in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
+        for nslots in (1, 4):
+            host = torch.from_numpy(P.U0.copy()).pin_memory()
+            hs = H.HostStream(P.mesh, host, P.packets, prec, nslots)
+            hs.run(args.warmup, P.cfl, P.gamma)
+            ts = time.perf_counter()
+            hs.run(args.steps, P.cfl, P.gamma)
+            el = time.perf_counter() - ts
+            hs.close()
+            out[f"{name}_slots{nslots}"] = {"cell_updates_per_s": cells * args.steps / el,
+                                            "ms_per_step": 1e3 * el / args.steps,
+                                            "pcie_gbs": 80.0 * cells * args.steps / el / 1e9}
+            log(name, nslots, json.dumps(out[f"{name}_slots{nslots}"]))
+    best = out["mixed_slots4"]
+    print(json.dumps({"metric": "cell-updates/s, host-resident packets (PCIe-inclusive), uneven workload, 1 MI355X",
+                      "value": best["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32 (PLM+HLLC) / f64 (state, recovery, update, dt)", "data": "synthetic (seeded)",
+                      "config": {"workload": f"uneven: {P.mesh.nblocks} self-periodic blocks, {cells} cells, "
+                                             f"{len(P.packets)} packets, state in pinned host memory"},
+                      "paths": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +250,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tune", action="store_true", help="autotune the batched launches first")
     ap.add_argument("--no-check", action="store_true", help="skip the one-step error check against the oracle")
+    ap.add_argument("--host-packets", action="store_true",
+                    help="instead: host-resident packets of the uneven workload streamed through device slots "
+                         "(PCIe-inclusive rate; prints its own line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
@@ -228,6 +266,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.host_packets:
+        return host_packets_bench(args)
     probe = copy_bandwidth()
     log("copy probe:", json.dumps(probe))
     t0 = time.perf_counter()

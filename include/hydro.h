@@ -209,6 +209,42 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
  * Errors: as hydro_batch_run. */
 hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *ms_out);
 
+/* ---------------------------------------------------------------------------
+ * Host-resident packets: the DataPacket life cycle of Sec. 4.3 (a packet's
+ * data moves to the device in one transfer, the task runs there, the result
+ * moves back) with the transfers hidden behind computation on GPU streams
+ * (Sec. 6.1).
+ *
+ * The state lives in a caller-owned host arena (layout as the device arena;
+ * pinned memory, e.g. from hipHostMalloc, lets the copies run asynchronously,
+ * pageable memory works but serialises them).  Packet p is the range of
+ * consecutive block ids [packet_start[p], packet_start[p+1]); its blocks must
+ * be stored back to back in the arena (offset of block b+1 = offset of block b
+ * + 5 * its cell count) and the packet must be closed (every HYDRO_NBR face
+ * of its blocks names a block of the same packet), so that it takes a full
+ * SSP-RK2 step on its own.  nslots (1..16) device staging slots, each with
+ * its own stream (default priority) and buffers sized for the largest packet,
+ * are used round robin: packet p is copied in, advanced (one launch per RK
+ * stage) and copied back on slot p mod nslots, so one packet's copies overlap
+ * other packets' kernels.  dt = cfl / max rate over all packets, from the
+ * state at the start of each step, stays on the device; steps are separated
+ * by a cross-stream join.  All device memory is allocated by create.
+ * Errors (create): EINVAL (descriptors as for hydro_mesh_create, packet
+ * ranges, non-contiguous packet, open packet, nslots, precision), ENOMEM,
+ * EDEVICE. */
+typedef struct hydro_stream hydro_stream;
+hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *host_arena,
+                                 int64_t arena_len, const int32_t *packet_start, int32_t npackets,
+                                 int32_t precision, int32_t nslots, hydro_stream **out);
+
+/* nsteps steps of every packet, in place in the host arena.  Synchronising;
+ * *t_out (may be NULL) receives the simulated time advanced.  Errors: EINVAL,
+ * ENONPHYS (the arena then holds the failing step's results of the packets
+ * already copied back), EDEVICE. */
+hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, double gamma, double *t_out);
+
+hydro_status hydro_stream_destroy(hydro_stream *s);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *hydro_last_error(void);
 

@@ -661,6 +661,233 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   return HYDRO_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------- host-resident packets
+struct hydro_stream {
+  int ndim = 3;
+  int prec = HYDRO_FP64;
+  int device = 0;
+  double *host = nullptr;
+  std::vector<hydro_block_desc> desc;
+  std::vector<int32_t> pstart;     // npackets + 1
+  std::vector<int64_t> phost;      // host element offset of each packet
+  std::vector<int64_t> plen;       // elements of each packet
+  std::vector<WorkList> wl;        // per packet, block ids into the shared table
+  DevBlock *d_blocks = nullptr;    // offsets relative to the packet's first block
+  struct Slot {
+    hipStream_t stream = nullptr;
+    double *state = nullptr;
+    double *u1 = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<Slot> slots;
+  hipStream_t ctl = nullptr;
+  hipEvent_t ready = nullptr;
+  DevTime *d_time = nullptr;
+};
+
+namespace {
+
+void stream_free(hydro_stream *s) {
+  for (auto &sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.state) (void)hipFree(sl.state);
+    if (sl.u1) (void)hipFree(sl.u1);
+  }
+  for (auto &w : s->wl)
+    if (w.d_items) (void)hipFree(w.d_items);
+  if (s->ready) (void)hipEventDestroy(s->ready);
+  if (s->ctl) (void)hipStreamDestroy(s->ctl);
+  if (s->d_blocks) (void)hipFree(s->d_blocks);
+  if (s->d_time) (void)hipFree(s->d_time);
+  delete s;
+}
+
+StageArgs slot_args(const hydro_stream *s, const hydro_stream::Slot &sl, const WorkList &wl, int stage, double gamma) {
+  StageArgs a;
+  a.blocks = s->d_blocks;
+  a.items = wl.d_items;
+  a.nitems = wl.nitems;
+  a.reset_time = 0;
+  a.xcd_remap = 1;
+  a.src = (stage == 1) ? sl.state : sl.u1;
+  a.un = sl.state;
+  a.dst = (stage == 1) ? sl.u1 : sl.state;
+  a.dt = 0.0;
+  a.dt_dev = s->d_time;
+  a.acc = s->d_time;
+  a.gamma = gamma;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *host_arena,
+                                 int64_t arena_len, const int32_t *packet_start, int32_t npackets,
+                                 int32_t precision, int32_t nslots, hydro_stream **out) {
+  if (!out) return fail(HYDRO_EINVAL, "stream: out is null");
+  *out = nullptr;
+  hydro_status st = validate_mesh(blocks, nblocks, ndim, host_arena, arena_len);
+  if (st) return st;
+  if (precision != HYDRO_FP64 && precision != HYDRO_FP32_FP64) return fail(HYDRO_EINVAL, "stream: bad precision");
+  if (nslots < 1 || nslots > 16) return fail(HYDRO_EINVAL, "stream: nslots must be in 1..16");
+  if (!packet_start || npackets < 1) return fail(HYDRO_EINVAL, "stream: need at least one packet");
+  if (packet_start[0] != 0 || packet_start[npackets] != nblocks)
+    return fail(HYDRO_EINVAL, "stream: packet ranges must start at 0 and end at nblocks");
+  for (int p = 0; p < npackets; ++p)
+    if (packet_start[p + 1] <= packet_start[p]) return fail(HYDRO_EINVAL, "stream: empty or decreasing packet range");
+  std::vector<int64_t> phost(npackets), plen(npackets);
+  int64_t maxlen = 0;
+  for (int p = 0; p < npackets; ++p) {
+    const int b0 = packet_start[p], b1 = packet_start[p + 1];
+    int64_t end = blocks[b0].offset;
+    for (int b = b0; b < b1; ++b) {
+      if (blocks[b].offset != end)
+        return fail(HYDRO_EINVAL, "stream: blocks of packet " + std::to_string(p) + " are not contiguous in the arena");
+      end += 5 * (int64_t)blocks[b].n[0] * blocks[b].n[1] * blocks[b].n[2];
+      for (int f = 0; f < 2 * ndim; ++f)
+        if (blocks[b].face_kind[f] == HYDRO_NBR && (blocks[b].nbr[f] < b0 || blocks[b].nbr[f] >= b1))
+          return fail(HYDRO_EINVAL, "stream: packet " + std::to_string(p) + " is not closed (block " +
+                                        std::to_string(b) + " links outside it)");
+    }
+    phost[p] = blocks[b0].offset;
+    plen[p] = end - blocks[b0].offset;
+    maxlen = std::max(maxlen, plen[p]);
+  }
+
+  hydro_stream *s = new hydro_stream();
+  s->ndim = ndim;
+  s->prec = precision;
+  s->host = host_arena;
+  s->desc.assign(blocks, blocks + nblocks);
+  s->pstart.assign(packet_start, packet_start + npackets + 1);
+  s->phost = phost;
+  s->plen = plen;
+  // block table with offsets relative to the first block of each block's packet
+  std::vector<hydro_block_desc> local(s->desc);
+  for (int p = 0; p < npackets; ++p)
+    for (int b = packet_start[p]; b < packet_start[p + 1]; ++b) local[b].offset -= phost[p];
+  std::vector<DevBlock> hb(nblocks);
+  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(local.data(), b, ndim);
+  auto bail = [&](hydro_status e, const std::string &msg) {
+    stream_free(s);
+    return fail(e, msg);
+  };
+  if (hipGetDevice(&s->device) != hipSuccess) return bail(HYDRO_EDEVICE, "stream: no HIP device");
+  if (hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess)
+    return bail(HYDRO_EDEVICE, "stream: control stream creation failed");
+  if (hipMalloc(&s->d_blocks, (size_t)nblocks * sizeof(DevBlock)) != hipSuccess)
+    return bail(HYDRO_ENOMEM, "stream: hipMalloc of the block table failed");
+  if (hipMemcpyAsync(s->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, s->ctl) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->ctl) != hipSuccess)
+    return bail(HYDRO_EDEVICE, "stream: block table upload failed");
+  if (alloc_time(&s->d_time, s->ctl)) return bail(HYDRO_ENOMEM, "stream: time record allocation failed");
+  // work lists: a throwaway mesh view for the item builder (descriptors only)
+  hydro_mesh view;
+  view.ndim = ndim;
+  view.nblocks = nblocks;
+  view.desc = s->desc;
+  s->wl.resize(npackets);
+  for (int p = 0; p < npackets; ++p) {
+    std::vector<int32_t> ids;
+    for (int b = packet_start[p]; b < packet_start[p + 1]; ++b) ids.push_back(b);
+    std::vector<WorkItem> items;
+    int kmask = 0;
+    build_items(&view, ids, {}, items, kmask);
+    if (upload_items(items, kmask, s->wl[p], s->ctl)) return bail(HYDRO_ENOMEM, "stream: work list upload failed");
+  }
+  s->slots.resize(nslots);
+  for (auto &sl : s->slots) {
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+      return bail(HYDRO_EDEVICE, "stream: slot stream creation failed");
+    if (hipMalloc(&sl.state, (size_t)maxlen * sizeof(double)) != hipSuccess ||
+        hipMalloc(&sl.u1, (size_t)maxlen * sizeof(double)) != hipSuccess)
+      return bail(HYDRO_ENOMEM, "stream: hipMalloc of a staging slot failed");
+  }
+  *out = s;
+  return HYDRO_OK;
+}
+
+hydro_status hydro_stream_destroy(hydro_stream *s) {
+  if (!s) return fail(HYDRO_EINVAL, "stream is null");
+  stream_free(s);
+  return HYDRO_OK;
+}
+
+hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, double gamma, double *t_out) {
+  if (!s) return fail(HYDRO_EINVAL, "stream is null");
+  if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
+  if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  const int np = (int)s->wl.size(), ns = (int)s->slots.size();
+  const bool mixed = s->prec == HYDRO_FP32_FP64;
+  auto ok = [](hipError_t e) { return e == hipSuccess; };
+  bool good = true;
+  // every slot stream starts after the control stream's last work
+  auto fan_out = [&]() {
+    good = good && ok(hipEventRecord(s->ready, s->ctl));
+    for (auto &sl : s->slots) good = good && ok(hipStreamWaitEvent(sl.stream, s->ready, 0));
+  };
+  auto join = [&]() {
+    for (auto &sl : s->slots) {
+      good = good && ok(hipEventRecord(sl.done, sl.stream));
+      good = good && ok(hipStreamWaitEvent(s->ctl, sl.done, 0));
+    }
+  };
+  auto copy_in = [&](int p, hydro_stream::Slot &sl) {
+    good = good && ok(hipMemcpyAsync(sl.state, s->host + s->phost[p], (size_t)s->plen[p] * sizeof(double),
+                                     hipMemcpyHostToDevice, sl.stream));
+  };
+  // dt of the first step: rate of every packet's current state
+  good = good && ok(hyd::launch_reset(s->d_time, s->ctl));
+  fan_out();
+  for (int p = 0; p < np && good; ++p) {
+    auto &sl = s->slots[p % ns];
+    copy_in(p, sl);
+    good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+                                         slot_args(s, sl, s->wl[p], 1, gamma)));
+  }
+  join();
+  good = good && ok(hyd::launch_finalize(s->d_time, cfl, 1, s->ctl));
+  for (int step = 0; step < nsteps && good; ++step) {
+    fan_out();
+    for (int p = 0; p < np && good; ++p) {
+      auto &sl = s->slots[p % ns];
+      copy_in(p, sl);
+      good = good && ok(hyd::launch_stage(s->ndim, mixed, 1, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+                                          slot_args(s, sl, s->wl[p], 1, gamma)));
+      good = good && ok(hyd::launch_stage(s->ndim, mixed, 2, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+                                          slot_args(s, sl, s->wl[p], 2, gamma)));
+      good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
+                                       hipMemcpyDeviceToHost, sl.stream));
+    }
+    join();
+    good = good && ok(hyd::launch_finalize(s->d_time, cfl, 0, s->ctl));
+  }
+  DevTime h;
+  if (good) good = ok(hipMemcpyAsync(&h, s->d_time, sizeof(DevTime), hipMemcpyDeviceToHost, s->ctl));
+  if (good) good = ok(hipStreamSynchronize(s->ctl));
+  if (!good) {
+    for (auto &sl : s->slots) (void)hipStreamSynchronize(sl.stream);
+    return fail(HYDRO_EDEVICE, std::string("stream run: ") + hipGetErrorString(hipGetLastError()));
+  }
+  if (h.status) return nonphys(h);
+  if (t_out) *t_out = h.t;
+  return HYDRO_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 // ------------------------------------------------------------------ tuning
 hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");

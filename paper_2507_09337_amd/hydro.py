@@ -76,6 +76,9 @@ def lib():
             "hydro_batch_autotune": [vp, dbl, i32],
             "hydro_batch_get_config": [vp, C.POINTER(C.c_int32), i32, C.POINTER(C.c_int32)],
             "hydro_batch_time_kernels": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
+            "hydro_stream_create": [C.POINTER(BlockDesc), i32, i32, vp, i64, C.POINTER(C.c_int32), i32, i32, i32, pp],
+            "hydro_stream_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
+            "hydro_stream_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -233,6 +236,42 @@ class Batch:
     def close(self):
         if self.h:
             _check(lib().hydro_batch_destroy(self.h), "hydro_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostStream:
+    """Host-resident packets streamed through device staging slots.
+
+    host_arena: a pinned CPU float64 torch tensor (or any object with
+    data_ptr() and numel(); pageable memory also works, without overlap).
+    packets: list of consecutive block-id ranges covering 0..nblocks-1."""
+
+    def __init__(self, block_mesh, host_arena, packets, precision: int = FP64, nslots: int = 4):
+        self._keep = host_arena
+        self._descs = descs_from_mesh(block_mesh)
+        starts = [int(p[0]) for p in packets] + [int(packets[-1][-1]) + 1]
+        st = (C.c_int32 * len(starts))(*starts)
+        h = C.c_void_p()
+        _check(lib().hydro_stream_create(self._descs, len(self._descs), int(block_mesh.ndim),
+                                         C.c_void_p(host_arena.data_ptr()), int(host_arena.numel()), st,
+                                         len(packets), int(precision), int(nslots), C.byref(h)),
+               "hydro_stream_create")
+        self.h = h
+
+    def run(self, nsteps: int, cfl: float, gamma: float) -> float:
+        t = C.c_double(0.0)
+        _check(lib().hydro_stream_run(self.h, int(nsteps), float(cfl), float(gamma), C.byref(t)), "hydro_stream_run")
+        return t.value
+
+    def close(self):
+        if self.h:
+            _check(lib().hydro_stream_destroy(self.h), "hydro_stream_destroy")
             self.h = None
 
     def __del__(self):

@@ -95,3 +95,32 @@ def test_bad_ndim_null_arena_and_null_handles():
     assert L.hydro_batch_create(None, 0, C.byref(out)) == H.EINVAL
     assert L.hydro_mesh_destroy(None) == H.EINVAL
     assert L.hydro_last_error()  # a message is set
+
+
+class _Host:
+    """Stand-in host arena (never dereferenced: validation fails first)."""
+
+    def __init__(self, n):
+        self.n = n
+
+    def data_ptr(self):
+        return 0x10000
+
+    def numel(self):
+        return self.n
+
+
+@pytest.mark.parametrize("case", ["ranges", "gap", "open"])
+def test_host_stream_rejects_bad_packets_on_host(case):
+    m = I.independent_blocks([8, 16, 8, 8], 3)
+    packets = [range(0, 2), range(2, 4)]
+    if case == "ranges":
+        packets = [range(0, 2), range(2, 3)]  # block 3 in no packet
+    elif case == "gap":
+        m.offset[1] += 8  # block 1 no longer follows block 0
+    else:
+        m.kind[0, 1] = I.NBR
+        m.nbr[0, 1] = 3  # links outside packet 0
+    with pytest.raises(H.HydroError) as e:
+        H.HostStream(m, _Host(m.arena_len + 64), packets)
+    assert e.value.code == H.EINVAL
