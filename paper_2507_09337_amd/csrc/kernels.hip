@@ -62,12 +62,15 @@ struct Arith<float> {  // hardware reciprocal and reciprocal square root (about 
   }
 };
 
-// minmod: the smaller-magnitude argument when both have the same strict sign, else 0.
+// minmod: the smaller-magnitude argument when both have the same strict sign,
+// else 0.  That is the median of (a, b, 0): both positive gives min(a, b), both
+// negative max(a, b), a sign change or a zero gives 0.  Four min/max
+// instructions, no compares or selects; the value equals the sign-tested form
+// (a zero result may carry either sign, which no later sum or product can see
+// except in the sign of a zero).
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
-  T pos = (a < b) ? a : b;
-  T neg = (a > b) ? a : b;
-  return (a > T(0) && b > T(0)) ? pos : ((a < T(0) && b < T(0)) ? neg : T(0));
+  return fmax(fmin(a, b), fmin(fmax(a, b), T(0)));
 }
 
 // PLM face states between w1 and w2 of four consecutive cells.
@@ -595,11 +598,9 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
 // minmod(W_i - W_{i-1}, W_{i+1} - W_i).
 // ------------------------------------------------------------------------
 
-// minmod by sign test: min(|a|, |b|) with the sign of a when a and b share a
-// strict sign, else 0 (the branch form's value; a zero result may carry a sign).
+// minmod in FP32 as the median of (a, b, 0): one v_med3_f32.
 __device__ __forceinline__ float minmod_f(float a, float b) {
-  const float m = __builtin_copysignf(fminf(fabsf(a), fabsf(b)), a);
-  return ((__float_as_int(a) ^ __float_as_int(b)) < 0) ? 0.0f : m;
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
 template <int TX>
@@ -949,8 +950,13 @@ constexpr size_t stage_lds_bytes() {
   return a > b ? a : b;
 }
 
+// Occupancy: the mixed tile's LDS (41 KiB per workgroup) admits three
+// workgroups, i.e. three waves per SIMD.  Stage 2 holds Un and the CFL rate
+// on top of stage 1's registers and would settle at two; it is held to the
+// register budget of three waves (a few spilled dwords, measured faster).
 template <int DIM, bool MIXED, int STAGE, int KMASK>
-__global__ __launch_bounds__(WG) void k_stage(StageArgs A) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((MIXED && STAGE == 2) ? 3 : 1)))
+void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
     // plain path: this launch precedes the stage-2 launch that accumulates
