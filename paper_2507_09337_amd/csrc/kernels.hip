@@ -585,14 +585,13 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
 }
 
 // ------------------------------------------------------------------------
-// Mixed-precision tile (FP32 PLM + HLLC): every minmod slope is computed once
-// per cell and direction, not once per face side.
+// Mixed-precision tile (FP32 PLM + HLLC).
 //
 // Per z plane j:  A) stage the plane's primitives and x/y guard ring in LDS;
-// B) each cell (and the guard cells next to the tile) forms its limited x and
-// y slopes and writes its two face states per direction; C) each face job
-// reads the two states of its face and runs HLLC; D) update.  The z slope is
-// carried down the column in registers (one minmod per cell per plane).
+// B) each face job reads the four primitives along its axis, forms the two
+// PLM states of the face and runs HLLC; C) update.  Two barriers per plane.
+// The z faces are formed in registers: the z slope of each cell is carried
+// down the column (one minmod per cell per plane).
 // Face states at cell i along an axis: plus = W_i + D_i/2 (left state of face
 // i+1/2), minus = W_i - D_i/2 (right state of face i-1/2), D_i =
 // minmod(W_i - W_{i-1}, W_{i+1} - W_i).
@@ -603,30 +602,27 @@ __device__ __forceinline__ float minmod_f(float a, float b) {
   return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
+// LDS layout of the mixed tile, per variable: the plane's primitives with
+// their two-cell x/y guard ring [TX+4 rows][TX+4] (corners unused), then the
+// x fluxes (faces 0..TX-1 of each row [row][face], then face TX [row]) and
+// the y fluxes [face 0..TX][x].
 template <int TX>
 struct SplitGeom {
   static constexpr int NT = TX * TX;
   static constexpr int PX = TX + 4;
-  static constexpr int PP = PX * PX;        // primitives with the x/y guard ring (corners unused)
-  static constexpr int SC = TX + 2;         // face-state cells along the swept axis: -1 .. TX
-  static constexpr int S = TX * SC;         // face states per variable, one direction and side
-  static constexpr int NF = (TX + 1) * TX;  // faces per variable and direction
+  static constexpr int PP = PX * PX;
+  static constexpr int NF = (TX + 1) * TX;  // faces per direction
   static constexpr int OW = 0;
-  static constexpr int OXP = OW + NVAR * PP;  // x plus states  [5][TX rows][SC]
-  static constexpr int OXM = OXP + NVAR * S;  // x minus states [5][TX rows][SC]
-  static constexpr int OYP = OXM + NVAR * S;  // y plus states  [5][SC rows][TX]
-  static constexpr int OYM = OYP + NVAR * S;  // y minus states [5][SC rows][TX]
-  static constexpr int OFX = OYM + NVAR * S;  // x fluxes [5][TX][TX+1]
-  static constexpr int OFY = OFX + NVAR * NF; // y fluxes [5][TX+1][TX]
+  static constexpr int OFX = OW + NVAR * PP;
+  static constexpr int OFY = OFX + NVAR * NF;
   static constexpr int ELEMS = OFY + NVAR * NF;
-  static constexpr int NJOB = (2 * NF + NT - 1) / NT;  // face jobs per thread per plane
 };
 
 template <int TX, int NSUB, int DIM, int STAGE>
 __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                                double dt, double &lam, int &bad, int &badblk) {
   using G = SplitGeom<TX>;
-  constexpr int NT = G::NT, PX = G::PX, PP = G::PP, SC = G::SC, S = G::S, NF = G::NF;
+  constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NF = G::NF;
   static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
   static_assert(8 * TX <= NT, "guard ring must fit the tile's threads");
 
@@ -643,26 +639,35 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   const float g32 = (float)gamma, rgm1 = (float)(1.0 / gm1);
   const double *__restrict__ src = A.src;
 
-  // face jobs of this thread, the same for every plane
-  int jl[G::NJOB], jr[G::NJOB], jo[G::NJOB];
-  bool jx[G::NJOB];
-#pragma unroll
-  for (int k = 0; k < G::NJOB; ++k) {
-    const int f = lt + k * NT;
-    jx[k] = f < NF;
-    if (f < NF) {  // x face `col` of row `row`: cells col-1 | col
-      const int row = f / (TX + 1), col = f % (TX + 1);
-      jl[k] = G::OXP + row * SC + col;
-      jr[k] = G::OXM + row * SC + col + 1;
-      jo[k] = G::OFX + row * (TX + 1) + col;
-    } else if (f < 2 * NF) {  // y face `row` of column `col`: cells row-1 | row
-      const int g = f - NF, row = g / TX, col = g % TX;
-      jl[k] = G::OYP + row * TX + col;
-      jr[k] = G::OYM + (row + 1) * TX + col;
-      jo[k] = G::OFY + row * TX + col;
-    } else {
-      jl[k] = jr[k] = jo[k] = -1;
-    }
+  // LDS slot of this thread's cell and of its second x flux
+  const int cw = (tj + 2) * PX + (ti + 2);
+  const int fx1 = (ti + 1 < TX) ? tj * TX + ti + 1 : TX * TX + tj;
+
+  // Face jobs of this thread, the same for every plane: job 0 is an x face,
+  // job 1 a y face, job 2 (threads < 2 TX) one of the TX x and TX y faces
+  // left over.  A job names the slot of the first of the four cells along
+  // its axis whose primitives give the face's two PLM states, and the slot
+  // of its flux.
+  static_assert(NF - NT == TX, "one leftover row of faces per direction");
+  auto xjob = [&](int f, int &wb, int &o) {  // x face `col` of row `row`: cells col-2 .. col+1
+    const int row = f / (TX + 1), col = f % (TX + 1);
+    wb = G::OW + (row + 2) * PX + col;
+    o = G::OFX + (col < TX ? row * TX + col : TX * TX + row);
+  };
+  auto yjob = [&](int g, int &wb, int &o) {  // y face `row` of column `col`: cells row-2 .. row+1
+    const int row = g / TX, col = g % TX;
+    wb = G::OW + row * PX + col + 2;
+    o = G::OFY + row * TX + col;
+  };
+  int jw0, jo0, jw1, jo1, jw2 = 0, jo2 = 0;
+  xjob(lt, jw0, jo0);
+  yjob(lt, jw1, jo1);
+  const bool has2 = lt < 2 * TX, x2 = lt < TX;
+  if (has2) {
+    if (x2)
+      xjob(NT + lt, jw2, jo2);
+    else
+      yjob(NT + lt - TX, jw2, jo2);
   }
 
   // Global loads are issued early and consumed late (software pipeline):
@@ -691,7 +696,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   auto stage_plane = [&](const float (&Wc)[5], const double (&Gr)[5]) {
     if (active) {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + (tj + 2) * PX + (ti + 2)] = Wc[v];
+      for (int v = 0; v < NVAR; ++v) L[G::OW + v * PP + cw] = Wc[v];
     }
     if (C.gslot >= 0) {
       float Wg[5];
@@ -701,72 +706,39 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     }
   };
 
-  // B) limited slopes and face states, x and y, of this thread's cell and of
-  // one guard cell beside the tile (threads < 4 TX)
-  auto slopes = [&](const float (&Wc)[5]) {
-    const int c = (tj + 2) * PX + (ti + 2);
+  // B) one face: the PLM states on both sides from the four cells starting
+  // at slot wb with stride st (1 along x, PX along y), then HLLC.  A y face
+  // swaps the two in-plane velocity components into the face frame and its
+  // flux back.
+  auto face = [&](int wb, int st, int o, bool isx) {
+    float a[5], r[5];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
-      const float *w = L + G::OW + v * PP;
-      const float wc = Wc[v];
-      const float mx = minmod_f(wc - w[c - 1], w[c + 1] - wc);
-      const float my = minmod_f(wc - w[c - PX], w[c + PX] - wc);
-      L[G::OXP + v * S + tj * SC + ti + 1] = wc + 0.5f * mx;
-      L[G::OXM + v * S + tj * SC + ti + 1] = wc - 0.5f * mx;
-      // y states are stored in the y-face frame (u and v swapped: slot 1 = normal)
-      L[G::OYP + v * S + (tj + 1) * TX + ti] = wc + 0.5f * my;
-      L[G::OYM + v * S + (tj + 1) * TX + ti] = wc - 0.5f * my;
+      const float *w = L + v * PP + wb;
+      const float w0 = w[0], w1 = w[st], w2 = w[2 * st], w3 = w[3 * st];
+      const float d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
+      a[v] = w1 + 0.5f * minmod_f(d01, d12);
+      r[v] = w2 - 0.5f * minmod_f(d12, d23);
     }
-    if (lt < 4 * TX) {
-      const bool xs = lt < 2 * TX;
-      const int l2 = xs ? lt : lt - 2 * TX;
-      const int side = l2 / TX, k = l2 % TX, e = side ? TX : -1;
-      // x: cell (e, row k), neighbours along x; y: cell (col k, e), along y
-      const int cc = xs ? (k + 2) * PX + (e + 2) : (e + 2) * PX + (k + 2);
-      const int st = xs ? 1 : PX;
-      const int so = xs ? k * SC + e + 1 : (e + 1) * TX + k;
-      const int op = xs ? G::OXP : G::OYP, om = xs ? G::OXM : G::OYM;
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        const float *w = L + G::OW + v * PP;
-        const float wc = w[cc];
-        const float m = minmod_f(wc - w[cc - st], w[cc + st] - wc);
-        L[op + v * S + so] = wc + 0.5f * m;
-        L[om + v * S + so] = wc - 0.5f * m;
-      }
-    }
+    const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
+    const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
+    float F[5];
+    hllc<float>(Lr, Rr, g32, rgm1, F);
+    float *q = L + o;
+    q[0] = F[0];
+    q[NF] = isx ? F[1] : F[2];
+    q[2 * NF] = isx ? F[2] : F[1];
+    q[3 * NF] = F[3];
+    q[4 * NF] = F[4];
   };
-
-  // C) HLLC on every x and y face of the plane
   auto faces = [&]() {
-#pragma unroll
-    for (int k = 0; k < G::NJOB; ++k) {
-      if (jl[k] < 0) continue;
-      const int vsS = S, vsF = NF;
-      float a[5], r[5];
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        a[v] = L[jl[k] + v * vsS];
-        r[v] = L[jr[k] + v * vsS];
-      }
-      // both directions' states are in their face frame; y fluxes stay in
-      // the y frame too (the update reads them with slots 1 and 2 swapped)
-      const bool isx = jx[k];
-      const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
-      const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
-      float F[5];
-      hllc<float>(Lr, Rr, g32, rgm1, F);
-      float *o = L + jo[k];
-      o[0] = F[0];
-      o[vsF] = isx ? F[1] : F[2];
-      o[2 * vsF] = isx ? F[2] : F[1];
-      o[3 * vsF] = F[3];
-      o[4 * vsF] = F[4];
-    }
+    face(jw0, 1, jo0, true);
+    face(jw1, PX, jo1, false);
+    if (has2) face(jw2, x2 ? 1 : PX, jo2, x2);
   };
 
   const double rdx0 = 1.0 / C.dx0, rdx1 = 1.0 / C.dx1, rdx2 = 1.0 / C.dx2;
-  // D) FP64 update of this thread's cell in plane z (FP32 fluxes widened);
+  // C) FP64 update of this thread's cell in plane z (FP32 fluxes widened);
   // Un is the prefetched stage-2 state of the cell
   auto update = [&](int z, const double (&Us)[5], const double (&Un)[5], const float (&fzlo)[5],
                     const float (&fzhi)[5]) {
@@ -775,9 +747,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     double Unew[5];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
-      const float *fx = L + G::OFX + v * NF + tj * (TX + 1) + ti;
+      const float *fx = L + G::OFX + v * NF;
       const float *fy = L + G::OFY + v * NF + tj * TX + ti;
-      double dU = C.dtdx * ((double)fx[0] - (double)fx[1]);
+      double dU = C.dtdx * ((double)fx[tj * TX + ti] - (double)fx[fx1]);
       dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
       if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
       Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
@@ -818,8 +790,6 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     if (active) prims(U, Wc, true);
     const float zero[5] = {0, 0, 0, 0, 0};
     stage_plane(Wc, Gr);
-    __syncthreads();
-    slopes(Wc);
     __syncthreads();
     faces();
     __syncthreads();
@@ -869,8 +839,6 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       fetch_un(j, Un);
       stage_plane(Wb, Gr);
       if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
-      __syncthreads();
-      slopes(Wb);
       __syncthreads();
       faces();
     }
