@@ -25,7 +25,8 @@
  *     minmod limiter (Roe 1986), one direction at a time, unsplit;
  *   - HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; Toro,
  *     "Riemann Solvers and Numerical Methods for Fluid Dynamics", 3rd ed.,
- *     ch. 10) with Davis (1988) wave-speed bounds;
+ *     ch. 10) with Davis (1988) wave-speed bounds, or, as a method variant,
+ *     Einfeldt's (1988) bounds from Roe-weighted averages (Toro sec. 10.5.1);
  *   - SSP-RK2 / TVD-RK2 (Shu & Osher 1988):
  *         U1   = Un + dt L(Un)
  *         Un+1 = 0.5 Un + 0.5 (U1 + dt L(U1));
@@ -63,6 +64,7 @@
 
 enum { ORACLE_NBR = 0, ORACLE_OUTFLOW = 1, ORACLE_PERIODIC_SELF = 2 };
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 3, ORACLE_ENONPHYS = 4 };
+enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1 };
 
 typedef struct {
   int32_t nblocks;
@@ -72,6 +74,7 @@ typedef struct {
   const int32_t *kind;   /* [nblocks][6] face kind for -x,+x,-y,+y,-z,+z */
   const int32_t *nbr;    /* [nblocks][6] neighbour block id of ORACLE_NBR faces */
   const int64_t *offset; /* [nblocks] element offset of variable 0 in the arena */
+  int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS or _EINFELDT */
 } oracle_mesh;
 
 /* ------------------------------------------------------------------------ */
@@ -190,12 +193,42 @@ void oracle_plm_face(const double *w, double *wl, double *wr) {
 }
 
 /*
+ * Bounds S = (S_L, S_R) of the wave speeds of the Riemann problem at a face
+ * whose normal is the first velocity component, c_K = sqrt(gamma p_K / rho_K).
+ *   Davis (1988):     S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).
+ *   Einfeldt (1988), as stated in Toro (2009) sec. 10.5.1:
+ *     with s_K = sqrt(rho_K), the Roe-weighted normal velocity
+ *       u_bar = (s_L u_L + s_R u_R) / (s_L + s_R),
+ *     d_bar^2 = (s_L c_L^2 + s_R c_R^2) / (s_L + s_R) + eta2 (u_R - u_L)^2,
+ *       eta2 = s_L s_R / (2 (s_L + s_R)^2),
+ *     S_L = u_bar - d_bar, S_R = u_bar + d_bar.
+ */
+void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int speeds, double *S) {
+  double rL = WL[0], uL = WL[1], pL = WL[4];
+  double rR = WR[0], uR = WR[1], pR = WR[4];
+  double cL = sqrt(gamma * pL / rL);
+  double cR = sqrt(gamma * pR / rR);
+  if (speeds == ORACLE_SPEEDS_EINFELDT) {
+    double sL = sqrt(rL), sR = sqrt(rR);
+    double ubar = (sL * uL + sR * uR) / (sL + sR);
+    double eta2 = 0.5 * sL * sR / ((sL + sR) * (sL + sR));
+    double dbar = sqrt((sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * (uR - uL) * (uR - uL));
+    S[0] = ubar - dbar;
+    S[1] = ubar + dbar;
+  } else {
+    double SL = fmin(uL - cL, uR - cR);
+    double SR = fmax(uL + cL, uR + cR);
+    S[0] = SL;
+    S[1] = SR;
+  }
+}
+
+/*
  * HLLC flux across a face whose normal is the first velocity component
  * (Toro 2009, sec. 10.4-10.6; Toro, Spruce & Speares 1994).
  * WL, WR = (rho, u_normal, u_t1, u_t2, p).  F = (mass, normal momentum,
  * t1 momentum, t2 momentum, energy) flux in the same frame.
- *   Wave speeds (Davis 1988): S_L = min(u_L - c_L, u_R - c_R),
- *                             S_R = max(u_L + c_L, u_R + c_R).
+ *   Wave speeds S_L, S_R: oracle_wave_speeds (Davis, or Einfeldt).
  *   Contact speed: S* = [p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)]
  *                       / [rho_L (S_L - u_L) - rho_R (S_R - u_R)].
  *   Star states:   U*_K = rho_K (S_K - u_K)/(S_K - S*) *
@@ -205,16 +238,15 @@ void oracle_plm_face(const double *w, double *wl, double *wr) {
  *          F_R + S_R (U*_R - U_R) if S* < 0 < S_R
  *          F_R                    if S_R <= 0.
  */
-void oracle_hllc(const double *WL, const double *WR, double gamma, double *F) {
+void oracle_hllc_speeds(const double *WL, const double *WR, double gamma, int speeds, double *F) {
   double rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
   double rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
   double EL = pL / (gamma - 1.0) + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
   double ER = pR / (gamma - 1.0) + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
-  double cL = sqrt(gamma * pL / rL);
-  double cR = sqrt(gamma * pR / rR);
 
-  double SL = fmin(uL - cL, uR - cR);
-  double SR = fmax(uL + cL, uR + cR);
+  double S[2];
+  oracle_wave_speeds(WL, WR, gamma, speeds, S);
+  double SL = S[0], SR = S[1];
   double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
 
   double UL[NVAR] = {rL, rL * uL, rL * vL, rL * wL, EL};
@@ -235,6 +267,11 @@ void oracle_hllc(const double *WL, const double *WR, double gamma, double *F) {
   } else {
     for (int v = 0; v < NVAR; ++v) F[v] = FR[v];
   }
+}
+
+/* HLLC with Davis wave speeds. */
+void oracle_hllc(const double *WL, const double *WR, double gamma, double *F) {
+  oracle_hllc_speeds(WL, WR, gamma, ORACLE_SPEEDS_DAVIS, F);
 }
 
 /* Local CFL rate of one cell: sum over active directions of (|u_d| + c)/dx_d. */
@@ -306,7 +343,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
           rl[1 + d] = wl[1];
           rr[1] = wr[1 + d];
           rr[1 + d] = wr[1];
-          oracle_hllc(rl, rr, gamma, f);
+          oracle_hllc_speeds(rl, rr, gamma, m->speeds, f);
           /* rotate back */
           double t = f[1];
           f[1] = f[1 + d];
@@ -357,6 +394,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
 int oracle_validate(const oracle_mesh *m) {
   if (!m || m->nblocks < 0 || (m->ndim != 2 && m->ndim != 3)) return ORACLE_EINVAL;
   if (m->nblocks > 0 && (!m->n || !m->dx || !m->kind || !m->nbr || !m->offset)) return ORACLE_EINVAL;
+  if (m->speeds != ORACLE_SPEEDS_DAVIS && m->speeds != ORACLE_SPEEDS_EINFELDT) return ORACLE_EINVAL;
   for (int b = 0; b < m->nblocks; ++b) {
     const int32_t *n = m->n + 3 * b;
     if (m->ndim == 2 && n[2] != 1) return ORACLE_EINVAL;

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libhydro_oracle.so")
 _OVERRIDE = os.environ.get("HYDRO_ORACLE_LIB")
 
 OK, EINVAL, ENOMEM, ENONPHYS = 0, 1, 3, 4
+DAVIS, EINFELDT = 0, 1  # HLLC wave-speed bounds
 
 
 class OracleError(RuntimeError):
@@ -39,6 +40,7 @@ class _Mesh(C.Structure):
         ("kind", C.POINTER(C.c_int32)),
         ("nbr", C.POINTER(C.c_int32)),
         ("offset", C.POINTER(C.c_int64)),
+        ("speeds", C.c_int32),
     ]
 
 
@@ -59,6 +61,8 @@ def lib():
         L.oracle_minmod.restype = C.c_double
         L.oracle_plm_face.argtypes = [dp, dp, dp]
         L.oracle_hllc.argtypes = [dp, dp, C.c_double, dp]
+        L.oracle_hllc_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
+        L.oracle_wave_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
         L.oracle_validate.argtypes = [mp]
         L.oracle_max_lambda.argtypes = [mp, dp, C.c_double, dp]
         L.oracle_step.argtypes = [mp, dp, C.c_double, C.c_double]
@@ -78,7 +82,7 @@ def _dptr(a: np.ndarray):
 class _MeshArgs:
     """Keeps the contiguous copies alive while the C struct points at them."""
 
-    def __init__(self, mesh):
+    def __init__(self, mesh, speeds: int = DAVIS):
         self.n = np.ascontiguousarray(mesh.n, dtype=np.int32)
         self.dx = np.ascontiguousarray(mesh.dx, dtype=np.float64)
         self.kind = np.ascontiguousarray(mesh.kind, dtype=np.int32)
@@ -92,6 +96,7 @@ class _MeshArgs:
             self.kind.ctypes.data_as(C.POINTER(C.c_int32)),
             self.nbr.ctypes.data_as(C.POINTER(C.c_int32)),
             self.offset.ctypes.data_as(C.POINTER(C.c_int64)),
+            int(speeds),
         )
 
     def ref(self):
@@ -122,18 +127,30 @@ def plm_face(w4) -> tuple[np.ndarray, np.ndarray]:
     return wl, wr
 
 
-def hllc(WL, WR, gamma: float) -> np.ndarray:
+def hllc(WL, WR, gamma: float, speeds: int = DAVIS) -> np.ndarray:
     """HLLC flux for states (rho, u_normal, u_t1, u_t2, p)."""
     a = np.ascontiguousarray(WL, dtype=np.float64)
     b = np.ascontiguousarray(WR, dtype=np.float64)
     f = np.empty(5)
-    lib().oracle_hllc(_dptr(a), _dptr(b), gamma, _dptr(f))
+    if speeds == DAVIS:
+        lib().oracle_hllc(_dptr(a), _dptr(b), gamma, _dptr(f))
+    else:
+        lib().oracle_hllc_speeds(_dptr(a), _dptr(b), gamma, int(speeds), _dptr(f))
     return f
 
 
+def wave_speeds(WL, WR, gamma: float, speeds: int = DAVIS) -> tuple[float, float]:
+    """(S_L, S_R) bounds of the Riemann fan used by HLLC."""
+    a = np.ascontiguousarray(WL, dtype=np.float64)
+    b = np.ascontiguousarray(WR, dtype=np.float64)
+    s = np.empty(2)
+    lib().oracle_wave_speeds(_dptr(a), _dptr(b), gamma, int(speeds), _dptr(s))
+    return float(s[0]), float(s[1])
+
+
 # ------------------------------------------------------------------- mesh
-def validate(mesh) -> int:
-    m = _MeshArgs(mesh)
+def validate(mesh, speeds: int = DAVIS) -> int:
+    m = _MeshArgs(mesh, speeds)
     return lib().oracle_validate(m.ref())
 
 
@@ -148,16 +165,16 @@ def dt(mesh, U: np.ndarray, gamma: float, cfl: float) -> float:
     return cfl / max_lambda(mesh, U, gamma)
 
 
-def step(mesh, U: np.ndarray, dt_: float, gamma: float) -> None:
+def step(mesh, U: np.ndarray, dt_: float, gamma: float, speeds: int = DAVIS) -> None:
     """One SSP-RK2 step of the whole mesh, in place."""
-    m = _MeshArgs(mesh)
+    m = _MeshArgs(mesh, speeds)
     _check(lib().oracle_step(m.ref(), _dptr(U), dt_, gamma), "step")
 
 
-def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets) -> np.ndarray:
+def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: int = DAVIS) -> np.ndarray:
     """One step for the listed blocks; returns a copy of U whose target blocks
     hold the new state (other blocks unchanged)."""
-    m = _MeshArgs(mesh)
+    m = _MeshArgs(mesh, speeds)
     t = np.ascontiguousarray(targets, dtype=np.int32)
     out = U.copy()
     _check(lib().oracle_step_subset(m.ref(), _dptr(U), dt_, gamma, t.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -165,9 +182,10 @@ def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets) -> np.nd
     return out
 
 
-def run(mesh, U: np.ndarray, nsteps: int, cfl: float, gamma: float, fixed_dt: float = 0.0):
+def run(mesh, U: np.ndarray, nsteps: int, cfl: float, gamma: float, fixed_dt: float = 0.0,
+        speeds: int = DAVIS):
     """nsteps steps in place; returns (dts array, t)."""
-    m = _MeshArgs(mesh)
+    m = _MeshArgs(mesh, speeds)
     dts = np.zeros(max(nsteps, 1))
     t = C.c_double(0.0)
     _check(lib().oracle_run(m.ref(), _dptr(U), int(nsteps), cfl, gamma, fixed_dt, _dptr(dts), C.byref(t)), "run")

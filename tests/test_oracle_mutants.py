@@ -14,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
-PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py"]
+PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py"]
 
 MUTANTS = {
     "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
@@ -33,6 +33,12 @@ MUTANTS = {
     "rk2-drops-un": ("Uout[a] = 0.5 * Un[a] + 0.5 * (src + d);", "Uout[a] = src + 0.5 * d;"),
     "cfl-uses-x-velocity": ("lam += (fabs(W[1 + d]) + c) / dx[d];", "lam += (fabs(W[1]) + c) / dx[d];"),
     "update-wrong-face": ("hi[d] += 1;", "hi[d] += 0;"),
+    "einfeldt-jump-factor": ("double eta2 = 0.5 * sL * sR", "double eta2 = sL * sR"),
+    "einfeldt-density-weights": ("double ubar = (sL * uL + sR * uR) / (sL + sR);",
+                                 "double ubar = (rL * uL + rR * uR) / (rL + rR);"),
+    "einfeldt-unweighted-c2": ("(sL * cL * cL + sR * cR * cR) / (sL + sR)", "(cL * cL + cR * cR) / 2.0"),
+    "einfeldt-step-uses-davis": ("oracle_hllc_speeds(rl, rr, gamma, m->speeds, f);",
+                                 "oracle_hllc_speeds(rl, rr, gamma, ORACLE_SPEEDS_DAVIS, f);"),
 }
 
 
