@@ -69,6 +69,11 @@ typedef enum {
   HYDRO_FP32_FP64 = 1 /* FP64 state, recovery, accumulation and dt; PLM + HLLC in FP32   */
 } hydro_precision;
 
+/* Method variant, OR-ed into a precision code: HLLC with Einfeldt's wave-speed
+ * bounds (sqrt(rho)-weighted mean normal velocity -+ d_bar, Toro sec. 10.5.1)
+ * instead of Davis's min/max of u -+ c.  Without it the bounds are Davis's. */
+#define HYDRO_SPEEDS_EINFELDT 0x100
+
 typedef enum {
   HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
   HYDRO_OUTFLOW = 1,      /* zero gradient: both guard layers copy the edge layer        */
@@ -111,7 +116,8 @@ hydro_status hydro_mesh_create(const hydro_block_desc *blocks, int32_t nblocks, 
 hydro_status hydro_mesh_destroy(hydro_mesh *m);
 
 /* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
- * listed blocks of mesh m, advanced in the given hydro_precision.  block_ids:
+ * listed blocks of mesh m, advanced in the given hydro_precision (optionally
+ * OR HYDRO_SPEEDS_EINFELDT).  block_ids:
  * host array of nblocks distinct ids.  Builds the packet's device work list.
  * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
  * EDEVICE. */
@@ -145,7 +151,8 @@ hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, d
 hydro_status hydro_packet_destroy(hydro_packet *p);
 
 /* A batch of packets of one mesh (all packets must share the mesh and the
- * precision; a block may appear in at most one packet of the batch).  Builds the concatenated device work
+ * precision code, wave-speed variant included; a block may appear in at most
+ * one packet of the batch).  Builds the concatenated device work
  * list used by the persistent batched launches.  Errors: EINVAL, ENOMEM,
  * EDEVICE. */
 hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, hydro_batch **out);

@@ -291,9 +291,18 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
-hydro_status launch_stage_wl(const hydro_mesh *m, bool mixed, int stage, const WorkList &wl, int grid,
+// A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
+// with HYDRO_SPEEDS_EINFELDT.
+bool prec_valid(int32_t p) {
+  const int32_t base = p & 0xff;
+  return (p & ~(0xff | HYDRO_SPEEDS_EINFELDT)) == 0 && (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
+}
+bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
+int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : 0; }
+
+hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a) {
-  hipError_t e = hyd::launch_stage(m->ndim, mixed, stage, wl.kmask, grid_of(wl, grid), s, a);
+  hipError_t e = hyd::launch_stage(m->ndim, is_mixed(prec), stage, wl.kmask, speeds_of(prec), grid_of(wl, grid), s, a);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return HYDRO_OK;
 }
@@ -383,7 +392,7 @@ hydro_status hydro_packet_create(hydro_mesh *m, const int32_t *block_ids, int32_
   *out = nullptr;
   if (!m) return fail(HYDRO_EINVAL, "packet: mesh is null");
   if (!block_ids || nblocks <= 0) return fail(HYDRO_EINVAL, "packet: need at least one block id");
-  if (precision != HYDRO_FP64 && precision != HYDRO_FP32_FP64) return fail(HYDRO_EINVAL, "packet: bad precision");
+  if (!prec_valid(precision)) return fail(HYDRO_EINVAL, "packet: bad precision");
   std::vector<char> seen(m->nblocks, 0);
   for (int i = 0; i < nblocks; ++i) {
     const int b = block_ids[i];
@@ -438,11 +447,11 @@ hydro_status hydro_packet_advance(hydro_packet *p, double dt, double gamma) {
   if (!p->closed)
     return fail(HYDRO_ESTATE, "packet is not closed under its NBR links; use a batch to keep stages synchronous");
   hydro_mesh *m = p->m;
-  const bool mixed = p->prec == HYDRO_FP32_FP64;
+  const int prec = p->prec;
   p->lam_valid = false;
-  st = launch_stage_wl(m, mixed, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
+  st = launch_stage_wl(m, prec, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
   if (st) return st;
-  st = launch_stage_wl(m, mixed, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
+  st = launch_stage_wl(m, prec, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
   if (st) return st;
   p->lam_valid = true;
   p->lam_gamma = gamma;
@@ -536,14 +545,14 @@ hydro_status hydro_batch_advance_plain(hydro_batch *b, double dt, double gamma) 
   hydro_status st = check_step_args(dt, gamma);
   if (st) return st;
   hydro_mesh *m = b->m;
-  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  const int prec = b->prec;
   for (auto *p : b->packets) {
     p->lam_valid = false;
-    st = launch_stage_wl(m, mixed, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
+    st = launch_stage_wl(m, prec, 1, p->wl, 0, m->stream, stage_args(m, p->wl, 1, dt, nullptr, p->d_time, gamma, 1));
     if (st) return st;
   }
   for (auto *p : b->packets) {
-    st = launch_stage_wl(m, mixed, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
+    st = launch_stage_wl(m, prec, 2, p->wl, 0, m->stream, stage_args(m, p->wl, 2, dt, nullptr, p->d_time, gamma, 0));
     if (st) return st;
     p->lam_valid = true;
     p->lam_gamma = gamma;
@@ -557,12 +566,12 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->gexec = nullptr;
   b->graph = nullptr;
-  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  const int prec = b->prec;
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hydro_status st =
-      launch_stage_wl(m, mixed, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+      launch_stage_wl(m, prec, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
   if (!st)
-    st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, b->cap_stream,
+    st = launch_stage_wl(m, prec, 2, b->wl, b->grid, b->cap_stream,
                          stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
   if (!st && hyd::launch_finalize(b->d_time, cfl, 0, b->cap_stream) != hipSuccess)
     st = fail(HYDRO_EDEVICE, "finalize launch failed");
@@ -617,7 +626,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   hydro_mesh *m = b->m;
-  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  const int prec = b->prec;
   for (auto *p : b->packets) p->lam_valid = false;
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
@@ -630,10 +639,10 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   hydro_status st = HYDRO_OK;
   HIP_TRY(hipEventRecord(ev[0], m->stream));
   for (int s = 0; s < nsteps && !st; ++s) {
-    st = launch_stage_wl(m, mixed, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+    st = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
     if (!st && hipEventRecord(ev[3 * s + 1], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st)
-      st = launch_stage_wl(m, mixed, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+      st = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
     if (!st && hipEventRecord(ev[3 * s + 2], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st && hyd::launch_finalize(b->d_time, cfl, 0, m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "finalize");
     if (!st && hipEventRecord(ev[3 * s + 3], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
@@ -734,7 +743,7 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
   *out = nullptr;
   hydro_status st = validate_mesh(blocks, nblocks, ndim, host_arena, arena_len);
   if (st) return st;
-  if (precision != HYDRO_FP64 && precision != HYDRO_FP32_FP64) return fail(HYDRO_EINVAL, "stream: bad precision");
+  if (!prec_valid(precision)) return fail(HYDRO_EINVAL, "stream: bad precision");
   if (nslots < 1 || nslots > 16) return fail(HYDRO_EINVAL, "stream: nslots must be in 1..16");
   if (!packet_start || npackets < 1) return fail(HYDRO_EINVAL, "stream: need at least one packet");
   if (packet_start[0] != 0 || packet_start[npackets] != nblocks)
@@ -828,7 +837,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   const int np = (int)s->wl.size(), ns = (int)s->slots.size();
-  const bool mixed = s->prec == HYDRO_FP32_FP64;
+  const int prec = s->prec;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   bool good = true;
   // every slot stream starts after the control stream's last work
@@ -862,9 +871,9 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
     for (int p = 0; p < np && good; ++p) {
       auto &sl = s->slots[p % ns];
       copy_in(p, sl);
-      good = good && ok(hyd::launch_stage(s->ndim, mixed, 1, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 1, s->wl[p].kmask, speeds_of(prec), s->wl[p].nitems, sl.stream,
                                           slot_args(s, sl, s->wl[p], 1, gamma)));
-      good = good && ok(hyd::launch_stage(s->ndim, mixed, 2, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 2, s->wl[p].kmask, speeds_of(prec), s->wl[p].nitems, sl.stream,
                                           slot_args(s, sl, s->wl[p], 2, gamma)));
       good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
                                        hipMemcpyDeviceToHost, sl.stream));
@@ -953,7 +962,7 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
 static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
                                 double &ms) {
   hydro_mesh *m = b->m;
-  const bool mixed = b->prec == HYDRO_FP32_FP64;
+  const int prec = b->prec;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -961,10 +970,10 @@ static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, in
   hydro_status st = HYDRO_OK;
   const double dt = 1e-30;  // the result is scratch; any positive dt
   StageArgs a = stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0, remap);
-  st = launch_stage_wl(m, mixed, 1, wl, grid, m->stream, a);  // warm-up
+  st = launch_stage_wl(m, prec, 1, wl, grid, m->stream, a);  // warm-up
   for (int r = 0; r < reps && !st; ++r) {
     (void)hipEventRecord(e0, m->stream);
-    st = launch_stage_wl(m, mixed, 1, wl, grid, m->stream, a);
+    st = launch_stage_wl(m, prec, 1, wl, grid, m->stream, a);
     (void)hipEventRecord(e1, m->stream);
     if (hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
     float f = 0;
@@ -988,7 +997,7 @@ static hydro_status stage1_sample(hydro_batch *b, const std::vector<int32_t> &id
   build_items(m, ids, cfg, items, kmask);
   hydro_status st = upload_items(items, kmask, wl, m->stream);
   if (st) return st;
-  st = launch_stage_wl(m, b->prec == HYDRO_FP32_FP64, 1, wl, 0, m->stream,
+  st = launch_stage_wl(m, b->prec, 1, wl, 0, m->stream,
                        stage_args(m, wl, 1, 1e-3, nullptr, b->d_time, gamma, 0));
   out.clear();
   for (int id : ids) {
@@ -1011,7 +1020,7 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
   if (reps < 1) return fail(HYDRO_EINVAL, "reps must be >= 1");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   hydro_mesh *m = b->m;
-  const double tol = (b->prec == HYDRO_FP32_FP64) ? 1e-6 : 1e-13;
+  const double tol = is_mixed(b->prec) ? 1e-6 : 1e-13;
   std::map<int, std::vector<int32_t>> cls;
   for (int id : b->ids) cls[block_class(m->desc[id], m->ndim)].push_back(id);
   for (auto &kv : cls) {

@@ -65,7 +65,9 @@ struct StageArgs {
 };
 
 // kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int grid, hipStream_t s, const StageArgs &a);
+// speeds: 0 = Davis, 1 = Einfeldt wave-speed bounds in HLLC.
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int grid, hipStream_t s,
+                        const StageArgs &a);
 hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a);
 hipError_t launch_reset(DevTime *t, hipStream_t s);
 hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s);

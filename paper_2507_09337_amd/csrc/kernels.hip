@@ -81,7 +81,12 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
   r = w2 - T(0.5) * minmod(d12, d23);
 }
 
-// HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).
+enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1 };
+
+// HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).  Wave
+// speed bounds: Davis, min/max of u -+ c over both sides; or Einfeldt,
+// u_bar -+ d_bar with sqrt(rho)-weighted u_bar and d_bar^2 = weighted mean of
+// c^2 + s_L s_R / (2 (s_L + s_R)^2) (u_R - u_L)^2 (Toro sec. 10.5.1).
 // The side of the contact is chosen first (left if S_L >= 0 or S* >= 0) and
 // only that side's physical flux and star state are formed:
 //   F = F_K + S (U*_K - U_K),  S = min(S_L, 0) on the left, max(S_R, 0) on the
@@ -89,13 +94,28 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
 // The star state is written with one reciprocal of (S_K - S*):
 //   q = (S_K - u)/(S_K - S*), rho* = rho q,
 //   E* = q E + rho* (S* - u) S* + (S* - u) p /(S_K - S*).
-template <typename T>
+template <typename T, int SPEEDS>
 __device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T F[5]) {
   using A = Arith<T>;
-  const T cL = A::sound(g, L[4], L[0]);
-  const T cR = A::sound(g, R[4], R[0]);
-  const T SL = fmin(L[1] - cL, R[1] - cR);
-  const T SR = fmax(L[1] + cL, R[1] + cR);
+  T SL, SR;
+  if constexpr (SPEEDS == SPEEDS_EINFELDT) {
+    // Einfeldt: u_bar -+ d_bar with sqrt(rho) weights s_K; c_K^2 = g p_K / rho_K = g p_K (1/s_K)^2
+    const T qL = __builtin_amdgcn_rsqf(L[0]), qR = __builtin_amdgcn_rsqf(R[0]);
+    const T sL = L[0] * qL, sR = R[0] * qR;
+    const T c2L = g * L[4] * qL * qL, c2R = g * R[4] * qR * qR;
+    const T is = A::rcp(sL + sR);
+    const T ub = (sL * L[1] + sR * R[1]) * is;
+    const T du = R[1] - L[1];
+    const T d2 = (sL * c2L + sR * c2R) * is + T(0.5) * sL * sR * is * is * du * du;
+    const T d = d2 * __builtin_amdgcn_rsqf(d2);
+    SL = ub - d;
+    SR = ub + d;
+  } else {
+    const T cL = A::sound(g, L[4], L[0]);
+    const T cR = A::sound(g, R[4], R[0]);
+    SL = fmin(L[1] - cL, R[1] - cR);
+    SR = fmax(L[1] + cL, R[1] + cR);
+  }
   const T aL = L[0] * (SL - L[1]);
   const T aR = R[0] * (SR - R[1]);
   const T Ss = A::div(R[4] - L[4] + aL * L[1] - aR * R[1], aL - aR);
@@ -124,19 +144,30 @@ __device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T 
 }
 
 // HLLC in FP64 with the operations in the order of the textbook statement
-// (left and right states, Davis speeds, S* from the jump relations, star state
+// (left and right states, Davis or Einfeldt speeds, S* from the jump relations, star state
 // rho_K (S_K - u)/(S_K - S*) (1, S*, v, w, E/rho + (S* - u)(S* + p/(rho (S_K - u))))),
 // no contraction into FMAs.  Division and square root are IEEE-correct on the
 // device, so each face flux is rounded exactly as in a plain FP64 CPU
 // evaluation of the same formulas.  Only the side K of the contact is formed.
+template <int SPEEDS>
 __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], double g, double F[5]) {
 #pragma clang fp contract(off)
   const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
   const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
   const double cL = __builtin_sqrt(g * pL / rL);
   const double cR = __builtin_sqrt(g * pR / rR);
-  const double SL = fmin(uL - cL, uR - cR);
-  const double SR = fmax(uL + cL, uR + cR);
+  double SL, SR;
+  if constexpr (SPEEDS == SPEEDS_EINFELDT) {
+    const double sL = __builtin_sqrt(rL), sR = __builtin_sqrt(rR);
+    const double ubar = (sL * uL + sR * uR) / (sL + sR);
+    const double eta2 = 0.5 * sL * sR / ((sL + sR) * (sL + sR));
+    const double dbar = __builtin_sqrt((sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * (uR - uL) * (uR - uL));
+    SL = ubar - dbar;
+    SR = ubar + dbar;
+  } else {
+    SL = fmin(uL - cL, uR - cR);
+    SR = fmax(uL + cL, uR + cR);
+  }
   const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
   const bool useL = (0.0 <= SL) || (0.0 <= Ss);
   const double r = useL ? rL : rR, u = useL ? uL : uR, v = useL ? vL : vR, w = useL ? wL : wR, p = useL ? pL : pR;
@@ -215,14 +246,14 @@ __device__ __forceinline__ double cell_rate(const double W[5], double gamma, dou
 
 // Face flux in the frame of direction d (normal velocity first), for either
 // precision.
-template <bool MIXED>
+template <bool MIXED, int SPEEDS>
 __device__ __forceinline__ void face_flux(const typename std::conditional<MIXED, float, double>::type L[5],
                                           const typename std::conditional<MIXED, float, double>::type R[5],
                                           double gamma, typename std::conditional<MIXED, float, double>::type F[5]) {
   if constexpr (MIXED)
-    hllc<float>(L, R, (float)gamma, (float)(1.0 / (gamma - 1.0)), F);
+    hllc<float, SPEEDS>(L, R, (float)gamma, (float)(1.0 / (gamma - 1.0)), F);
   else
-    hllc_fp64(L, R, gamma, F);
+    hllc_fp64<SPEEDS>(L, R, gamma, F);
 }
 
 // Source of an out-of-block cell along one axis: face f's source block and
@@ -354,7 +385,7 @@ __device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const
 // One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
 // marched over z planes [z0, z1).
 // ------------------------------------------------------------------------
-template <int TX, int TY, int NSUB, int DIM, bool MIXED, int STAGE>
+template <int TX, int TY, int NSUB, int DIM, bool MIXED, int STAGE, int SPEEDS>
 __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                          double dt, double &lam, int &bad, int &badblk) {
   using T = typename std::conditional<MIXED, float, double>::type;
@@ -457,7 +488,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
       const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
       T Fr[5];
-      face_flux<MIXED>(Lr, Rr, gamma, Fr);
+      face_flux<MIXED, SPEEDS>(Lr, Rr, gamma, Fr);
       out[0] = Fr[0];
       out[ostride] = isx ? Fr[1] : Fr[2];
       out[2 * ostride] = isx ? Fr[2] : Fr[1];
@@ -561,7 +592,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
       const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
       T Fr[5];
-      face_flux<MIXED>(Lr, Rr, gamma, Fr);
+      face_flux<MIXED, SPEEDS>(Lr, Rr, gamma, Fr);
       fz[0] = Fr[0];
       fz[1] = Fr[3];
       fz[2] = Fr[2];
@@ -618,7 +649,7 @@ struct SplitGeom {
   static constexpr int ELEMS = OFY + NVAR * NF;
 };
 
-template <int TX, int NSUB, int DIM, int STAGE>
+template <int TX, int NSUB, int DIM, int STAGE, int SPEEDS>
 __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                                double dt, double &lam, int &bad, int &badblk) {
   using G = SplitGeom<TX>;
@@ -723,7 +754,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
     const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
     float F[5];
-    hllc<float>(Lr, Rr, g32, rgm1, F);
+    hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
     float *q = L + o;
     q[0] = F[0];
     q[NF] = isx ? F[1] : F[2];
@@ -858,7 +889,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       const float Lr[5] = {zp[0], zp[3], zp[2], zp[1], zp[4]};
       const float Rr[5] = {zr[0], zr[3], zr[2], zr[1], zr[4]};
       float F[5];
-      hllc<float>(Lr, Rr, g32, rgm1, F);
+      hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
       fz[0] = F[0];
       fz[1] = F[3];
       fz[2] = F[2];
@@ -922,7 +953,7 @@ constexpr size_t stage_lds_bytes() {
 // workgroups, i.e. three waves per SIMD.  Stage 2 holds Un and the CFL rate
 // on top of stage 1's registers and would settle at two; it is held to the
 // register budget of three waves (a few spilled dwords, measured faster).
-template <int DIM, bool MIXED, int STAGE, int KMASK>
+template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((MIXED && STAGE == 2) ? 3 : 1)))
 void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
@@ -940,14 +971,14 @@ void k_stage(StageArgs A) {
     const WorkItem *it = A.items + i;
     if constexpr (MIXED) {
       if ((KMASK & 1) && it->kind == KIND_T16)
-        run_tile_mixed<16, 1, DIM, STAGE>(A, it, lds, dt, lam, bad, badblk);
+        run_tile_mixed<16, 1, DIM, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
       else if (KMASK & 2)
-        run_tile_mixed<8, 4, DIM, STAGE>(A, it, lds, dt, lam, bad, badblk);
+        run_tile_mixed<8, 4, DIM, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
     } else {
       if ((KMASK & 1) && it->kind == KIND_T16)
-        run_tile<16, 16, 1, DIM, false, STAGE>(A, it, lds, dt, lam, bad, badblk);
+        run_tile<16, 16, 1, DIM, false, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
       else if (KMASK & 2)
-        run_tile<8, 8, 4, DIM, false, STAGE>(A, it, lds, dt, lam, bad, badblk);
+        run_tile<8, 8, 4, DIM, false, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -1012,30 +1043,38 @@ __global__ void k_finalize(DevTime *t, double cfl, int init) {
 // ------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------
-template <int DIM, bool MIXED, int STAGE>
-static hipError_t launch_k(int kmask, int grid, hipStream_t s, const StageArgs &a) {
+template <int DIM, bool MIXED, int STAGE, int SPEEDS>
+static hipError_t launch_ks(int kmask, int grid, hipStream_t s, const StageArgs &a) {
   switch (kmask) {
     case 1:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int grid, hipStream_t s, const StageArgs &a) {
+template <int DIM, bool MIXED, int STAGE>
+static hipError_t launch_k(int kmask, int speeds, int grid, hipStream_t s, const StageArgs &a) {
+  return speeds == SPEEDS_EINFELDT ? launch_ks<DIM, MIXED, STAGE, SPEEDS_EINFELDT>(kmask, grid, s, a)
+                                   : launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS>(kmask, grid, s, a);
+}
+
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int grid, hipStream_t s,
+                        const StageArgs &a) {
   if (grid <= 0) return hipSuccess;
+  const int k = kmask, w = speeds;
   if (ndim == 2) {
-    if (mixed) return stage == 1 ? launch_k<2, true, 1>(kmask, grid, s, a) : launch_k<2, true, 2>(kmask, grid, s, a);
-    return stage == 1 ? launch_k<2, false, 1>(kmask, grid, s, a) : launch_k<2, false, 2>(kmask, grid, s, a);
+    if (mixed) return stage == 1 ? launch_k<2, true, 1>(k, w, grid, s, a) : launch_k<2, true, 2>(k, w, grid, s, a);
+    return stage == 1 ? launch_k<2, false, 1>(k, w, grid, s, a) : launch_k<2, false, 2>(k, w, grid, s, a);
   }
-  if (mixed) return stage == 1 ? launch_k<3, true, 1>(kmask, grid, s, a) : launch_k<3, true, 2>(kmask, grid, s, a);
-  return stage == 1 ? launch_k<3, false, 1>(kmask, grid, s, a) : launch_k<3, false, 2>(kmask, grid, s, a);
+  if (mixed) return stage == 1 ? launch_k<3, true, 1>(k, w, grid, s, a) : launch_k<3, true, 2>(k, w, grid, s, a);
+  return stage == 1 ? launch_k<3, false, 1>(k, w, grid, s, a) : launch_k<3, false, 2>(k, w, grid, s, a);
 }
 
 hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a) {

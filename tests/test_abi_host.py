@@ -124,3 +124,26 @@ def test_host_stream_rejects_bad_packets_on_host(case):
     with pytest.raises(H.HydroError) as e:
         H.HostStream(m, _Host(m.arena_len + 64), packets)
     assert e.value.code == H.EINVAL
+
+
+@pytest.mark.parametrize("prec", [2, 0x200, 0x101 | 0x1000, -1])
+def test_bad_precision_codes_rejected_on_host(prec):
+    m = I.independent_blocks([8, 8], 3)
+    with pytest.raises(H.HydroError) as e:
+        H.HostStream(m, _Host(m.arena_len), [range(0, 1), range(1, 2)], prec)
+    assert e.value.code == H.EINVAL and "precision" in str(e.value)
+
+
+@pytest.mark.parametrize("prec", [H.FP64 | H.EINFELDT, H.FP32_FP64 | H.EINFELDT])
+def test_einfeldt_variant_passes_host_validation(prec):
+    """A valid code with the wave-speed flag gets past every host check; with
+    no GPU the first device call then fails loudly."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("host-only check (the stand-in arena is not real memory)")
+    m = I.independent_blocks([8, 8], 3)
+    try:
+        H.HostStream(m, _Host(m.arena_len), [range(0, 1), range(1, 2)], prec).close()
+    except H.HydroError as e:
+        assert e.code in (H.EDEVICE, H.ENOMEM), str(e)
