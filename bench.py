@@ -316,6 +316,17 @@ def main():
                                             for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
 
+    # method variant (Einfeldt wave speeds): kernel time of a few eager steps
+    variants = {}
+    for name, prec in (("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT), ("fp64_einfeldt", H.FP64 | H.EINFELDT)):
+        arena.copy_(U0_dev)
+        b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+        k = b.time_kernels(min(args.steps, 5), P.cfl, P.gamma)
+        b.close()
+        variants[name] = {"stage_ms_per_step": k["stage1_ms"] + k["stage2_ms"],
+                          "cell_updates_per_s": cells / ((k["stage1_ms"] + k["stage2_ms"]) * 1e-3)}
+        log(name, json.dumps(variants[name]))
+
     if not args.no_plain:
         arena.copy_(U0_dev)
         b = H.Batch(pk64)
@@ -365,8 +376,8 @@ def main():
     km = kernel_ms["batched_mixed"]
     stage_ms = km["stage1_ms"] + km["stage2_ms"]
     achieved = BYTES_PER_CELL_UPDATE * cells / (stage_ms * 1e-3) / 1e9
-    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1>(hyd::StageArgs)",
-                                "void hyd::k_stage<3, true, 2, 1>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
+    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0>(hyd::StageArgs)",
+                                "void hyd::k_stage<3, true, 2, 1, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
@@ -404,6 +415,7 @@ def main():
         "batched_fp64_roofline_frac": ach64 / HBM_PEAK_GBS,
         "tuning": results["batched_mixed"]["config"],
         "errors_vs_oracle": errs,
+        "variants_kernel_time": variants,
     }
     if "plain_fp64" in results:
         line["speedup_vs_plain_fp64"] = head["cell_updates_per_s"] / results["plain_fp64"]["cell_updates_per_s"]
