@@ -441,7 +441,11 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     if (gslot >= 0) fetch(src + goff + (int64_t)z * gps, gvs, G);
   };
   auto fetch_un = [&](int z, double (&Un)[5]) {
-    if (STAGE == 2 && active) fetch(A.un + boff + (int64_t)z * plane + cidx, own_vs, Un);
+    if (STAGE == 2 && active) {  // Un is read once, pointwise: streamed in
+      const double *p = A.un + boff + (int64_t)z * plane + cidx;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Un[v] = __builtin_nontemporal_load(&p[v * own_vs]);
+    }
   };
 
   // stage the x/y guard ring and this thread's cell of the plane into LDS
@@ -515,7 +519,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       dU += dtdy * (fyl - fyh);
       if (DIM == 3) dU += dtdz * ((double)fzlo[v] - (double)fzhi[v]);
       Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
-      A.dst[boff + v * own_vs + c + cidx] = Unew[v];
+      __builtin_nontemporal_store(Unew[v], &A.dst[boff + v * own_vs + c + cidx]);  // streamed out
     }
     if (STAGE == 2) {  // CFL rate of the new state (FP64)
       double W[5];
@@ -784,7 +788,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
       if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
       Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
-      (A.dst + C.boff)[(int64_t)v * C.ncell + (int)c] = Unew[v];
+      // streamed out: the stage result is not read again in this launch, so it
+      // must not evict the neighbours' cells that the guard reads hit in L2
+      __builtin_nontemporal_store(Unew[v], &(A.dst + C.boff)[(int64_t)v * C.ncell + (int)c]);
     }
     if (STAGE == 2) {  // CFL rate of the new state in FP64: c = g p / sqrt(g p rho), refined rsq
       double W[5];
@@ -807,7 +813,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       const double *__restrict__ ub = A.un + C.boff;
       const int o = z * (int)C.plane + (int)C.cidx;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) Un[v] = ub[(int64_t)v * C.ncell + o];
+      for (int v = 0; v < NVAR; ++v) Un[v] = __builtin_nontemporal_load(&ub[(int64_t)v * C.ncell + o]);  // read once
     }
   };
 
