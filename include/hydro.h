@@ -231,9 +231,10 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
  * of its blocks names a block of the same packet), so that it takes a full
  * SSP-RK2 step on its own.  nslots (1..16) device staging slots, each with
  * its own stream (default priority) and buffers sized for the largest packet,
- * are used round robin: packet p is copied in, advanced (one launch per RK
- * stage) and copied back on slot p mod nslots, so one packet's copies overlap
- * other packets' kernels.  dt = cfl / max rate over all packets, from the
+ * take the packets in order, each packet going to the slot with the fewest
+ * bytes so far: packet p is copied in, advanced (one launch per RK stage) and
+ * copied back on its slot's stream, so one packet's copies overlap other
+ * packets' copies and kernels.  dt = cfl / max rate over all packets, from the
  * state at the start of each step, stays on the device; steps are separated
  * by a cross-stream join.  All device memory is allocated by create.
  * Errors (create): EINVAL (descriptors as for hydro_mesh_create, packet

@@ -691,6 +691,7 @@ struct hydro_stream {
     hipEvent_t done = nullptr;
   };
   std::vector<Slot> slots;
+  std::vector<int> pslot;  // slot of each packet: the least loaded so far, in packet order
   hipStream_t ctl = nullptr;
   hipEvent_t ready = nullptr;
   DevTime *d_time = nullptr;
@@ -813,6 +814,15 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
     if (upload_items(items, kmask, s->wl[p], s->ctl)) return bail(HYDRO_ENOMEM, "stream: work list upload failed");
   }
   s->slots.resize(nslots);
+  // packets of uneven size: each goes to the slot with the fewest bytes so far,
+  // so the slot streams finish a step together
+  std::vector<int64_t> load(nslots, 0);
+  s->pslot.resize(npackets);
+  for (int p = 0; p < npackets; ++p) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    s->pslot[p] = k;
+    load[k] += plen[p];
+  }
   for (auto &sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
@@ -836,7 +846,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
-  const int np = (int)s->wl.size(), ns = (int)s->slots.size();
+  const int np = (int)s->wl.size();
   const int prec = s->prec;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   bool good = true;
@@ -859,7 +869,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   good = good && ok(hyd::launch_reset(s->d_time, s->ctl));
   fan_out();
   for (int p = 0; p < np && good; ++p) {
-    auto &sl = s->slots[p % ns];
+    auto &sl = s->slots[s->pslot[p]];
     copy_in(p, sl);
     good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
                                          slot_args(s, sl, s->wl[p], 1, gamma)));
@@ -869,7 +879,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   for (int step = 0; step < nsteps && good; ++step) {
     fan_out();
     for (int p = 0; p < np && good; ++p) {
-      auto &sl = s->slots[p % ns];
+      auto &sl = s->slots[s->pslot[p]];
       copy_in(p, sl);
       good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 1, s->wl[p].kmask, speeds_of(prec), s->wl[p].nitems, sl.stream,
                                           slot_args(s, sl, s->wl[p], 1, gamma)));

@@ -8,8 +8,10 @@ CPU fallback).
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 import re
+import tempfile
 import weakref
 
 import numpy as np
@@ -223,8 +225,47 @@ class Batch:
     def set_launch(self, grid: int, xcd_remap: int = 1):
         _check(lib().hydro_batch_set_launch(self.h, int(grid), int(xcd_remap)), "hydro_batch_set_launch")
 
-    def autotune(self, gamma: float, reps: int = 3):
+    def autotune(self, gamma: float, reps: int = 3, cache: str | None = None) -> dict:
+        """Tune the batched launches in the library (tiling per block class,
+        then grid and XCD renumbering; every candidate parity-checked) and
+        return the chosen configuration.  cache: path of a JSON file of earlier
+        results, keyed by device, precision code, dimension and block classes;
+        a stored entry is applied without timing, a new result is added."""
+        key = self.tuning_key()
+        data = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+            if key in data:
+                self.apply_config(data[key])
+                return data[key]
         _check(lib().hydro_batch_autotune(self.h, float(gamma), int(reps)), "hydro_batch_autotune")
+        cfg = self.config()
+        if cache:
+            data[key] = cfg
+            d = os.path.dirname(os.path.abspath(cache))
+            fd, tmp = tempfile.mkstemp(dir=d, suffix=".json")
+            with os.fdopen(fd, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return cfg
+
+    def tuning_key(self) -> str:
+        """Device | precision code | ndim | (class edge: cells, ...) of this batch."""
+        try:
+            import torch
+
+            dev = torch.cuda.get_device_name(torch.cuda.current_device())
+        except Exception:
+            dev = "gpu"
+        classes = ",".join(f"{c['edge']}:{c['cells']}" for c in self.config()["classes"])
+        return f"{dev}|prec={self.packets[0].precision}|ndim={self.packets[0].mesh.ndim}|{classes}"
+
+    def apply_config(self, cfg: dict):
+        """Apply a configuration as returned by config() / autotune()."""
+        for c in cfg["classes"]:
+            self.set_tiling(c["edge"], c["tile"], c["zchunk"])
+        self.set_launch(cfg["grid"], cfg["xcd_remap"])
 
     def config(self) -> dict:
         buf = (C.c_int32 * (2 + 4 * 16))()

@@ -255,3 +255,28 @@ def test_host_resident_packets_match_device_batch_and_oracle():
             assert np.array_equal(U, U_dev) and t == t_dev, (prec, nslots)
         if prec == H.FP64:
             assert rel_err(P.mesh, U_dev, R) <= TOL64
+
+
+def test_autotune_results_cached_as_json(tmp_path):
+    """The tuned configuration is stored under the batch's key; a second batch
+    of the same shape takes it from the file without timing and computes the
+    same result."""
+    import json
+
+    P = I.uneven(nblocks=60, nsteps=4)
+    cache = str(tmp_path / "tuning.json")
+    outs = []
+    for k in range(2):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, ids, H.FP32_FP64) for ids in P.packets])
+        cfg = b.autotune(P.gamma, reps=1, cache=cache)
+        assert b.config() == cfg
+        with open(cache) as f:
+            assert json.load(f)[b.tuning_key()] == cfg
+        b.run(P.nsteps, P.cfl, P.gamma)
+        outs.append((cfg, to_host(arena)))
+        b.close()
+        mesh.close()
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
