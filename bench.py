@@ -217,7 +217,7 @@ def host_packets_bench(args):
     cells = P.mesh.total_cells
     out = {}
     for prec, name in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
-        for nslots in (1, 4):
+        for nslots in (1, 3, 4):
             host = torch.from_numpy(P.U0.copy()).pin_memory()
             hs = H.HostStream(P.mesh, host, P.packets, prec, nslots)
             hs.run(args.warmup, P.cfl, P.gamma)
@@ -229,7 +229,7 @@ def host_packets_bench(args):
                                             "ms_per_step": 1e3 * el / args.steps,
                                             "pcie_gbs": 80.0 * cells * args.steps / el / 1e9}
             log(name, nslots, json.dumps(out[f"{name}_slots{nslots}"]))
-    best = out["mixed_slots4"]
+    best = max((v for k, v in out.items() if k.startswith("mixed")), key=lambda v: v["cell_updates_per_s"])
     print(json.dumps({"metric": "cell-updates/s, host-resident packets (PCIe-inclusive), uneven workload, 1 MI355X",
                       "value": best["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],

@@ -235,8 +235,10 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
  * bytes so far: packet p is copied in, advanced (one launch per RK stage) and
  * copied back on its slot's stream, so one packet's copies overlap other
  * packets' copies and kernels.  dt = cfl / max rate over all packets, from the
- * state at the start of each step, stays on the device; steps are separated
- * by a cross-stream join.  All device memory is allocated by create.
+ * state at the start of each step, stays on the device: the control stream
+ * waits for every slot's last stage-2 launch of a step, updates dt, and each
+ * slot waits for that update only after it has issued the copy-in of its
+ * first packet of the next step.  All device memory is allocated by create.
  * Errors (create): EINVAL (descriptors as for hydro_mesh_create, packet
  * ranges, non-contiguous packet, open packet, nslots, precision), ENOMEM,
  * EDEVICE. */

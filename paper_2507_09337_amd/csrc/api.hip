@@ -850,16 +850,17 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   const int prec = s->prec;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   bool good = true;
+  const int ns = (int)s->slots.size();
+  std::vector<int> lastp(ns, -1);  // last packet of each slot
+  for (int p = 0; p < np; ++p) lastp[s->pslot[p]] = p;
   // every slot stream starts after the control stream's last work
   auto fan_out = [&]() {
     good = good && ok(hipEventRecord(s->ready, s->ctl));
     for (auto &sl : s->slots) good = good && ok(hipStreamWaitEvent(sl.stream, s->ready, 0));
   };
-  auto join = [&]() {
-    for (auto &sl : s->slots) {
-      good = good && ok(hipEventRecord(sl.done, sl.stream));
-      good = good && ok(hipStreamWaitEvent(s->ctl, sl.done, 0));
-    }
+  auto done = [&](hydro_stream::Slot &sl) {  // the control stream waits for this slot's work so far
+    good = good && ok(hipEventRecord(sl.done, sl.stream));
+    good = good && ok(hipStreamWaitEvent(s->ctl, sl.done, 0));
   };
   auto copy_in = [&](int p, hydro_stream::Slot &sl) {
     good = good && ok(hipMemcpyAsync(sl.state, s->host + s->phost[p], (size_t)s->plen[p] * sizeof(double),
@@ -873,24 +874,36 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
     copy_in(p, sl);
     good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
                                          slot_args(s, sl, s->wl[p], 1, gamma)));
+    if (p == lastp[s->pslot[p]]) done(sl);
   }
-  join();
   good = good && ok(hyd::launch_finalize(s->d_time, cfl, 1, s->ctl));
+  good = good && ok(hipEventRecord(s->ready, s->ctl));
+  // Each step: a slot copies its first packet in before it waits for the new
+  // dt (the copies of one step's tail and the next step's head overlap the
+  // dt update); the control stream waits for every slot's last stage-2 launch
+  // (not its copy-out) before it computes the next dt.
   for (int step = 0; step < nsteps && good; ++step) {
-    fan_out();
+    std::vector<char> waited(ns, 0);
     for (int p = 0; p < np && good; ++p) {
-      auto &sl = s->slots[s->pslot[p]];
+      const int k = s->pslot[p];
+      auto &sl = s->slots[k];
       copy_in(p, sl);
-      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 1, s->wl[p].kmask, speeds_of(prec), s->wl[p].nitems, sl.stream,
-                                          slot_args(s, sl, s->wl[p], 1, gamma)));
-      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 2, s->wl[p].kmask, speeds_of(prec), s->wl[p].nitems, sl.stream,
-                                          slot_args(s, sl, s->wl[p], 2, gamma)));
+      if (!waited[k]) {
+        good = good && ok(hipStreamWaitEvent(sl.stream, s->ready, 0));
+        waited[k] = 1;
+      }
+      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 1, s->wl[p].kmask, speeds_of(prec),
+                                          s->wl[p].nitems, sl.stream, slot_args(s, sl, s->wl[p], 1, gamma)));
+      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 2, s->wl[p].kmask, speeds_of(prec),
+                                          s->wl[p].nitems, sl.stream, slot_args(s, sl, s->wl[p], 2, gamma)));
+      if (p == lastp[k]) done(sl);
       good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
                                        hipMemcpyDeviceToHost, sl.stream));
     }
-    join();
     good = good && ok(hyd::launch_finalize(s->d_time, cfl, 0, s->ctl));
+    good = good && ok(hipEventRecord(s->ready, s->ctl));
   }
+  for (auto &sl : s->slots) done(sl);  // the last copies back
   DevTime h;
   if (good) good = ok(hipMemcpyAsync(&h, s->d_time, sizeof(DevTime), hipMemcpyDeviceToHost, s->ctl));
   if (good) good = ok(hipStreamSynchronize(s->ctl));
