@@ -5,14 +5,15 @@
 // halo, 2nd-order Runge-Kutta refreshing guards before each stage; Sec. 5.2:
 // ideal-gas gamma-law EOS).  Reconstruction and flux follow the textbook
 // methods named in include/hydro.h: PLM on primitives with minmod, HLLC with
-// Davis wave speeds, SSP-RK2 combine, CFL rate sum_d (|u_d| + c)/dx_d.
+// Davis (or, as a variant, Einfeldt) wave speeds, SSP-RK2 combine, CFL rate
+// sum_d (|u_d| + c)/dx_d.
 //
 // Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
 //   * One workgroup = 256 threads = one x-y tile of a block (16x16) or four
 //     independent 8x8 tiles (one per wave).  The workgroup marches its tile
 //     column through the z planes of the block ("2.5-D"): the z direction
-//     lives in registers (a four-plane sliding window of primitives per
-//     thread, so every z face is computed once by the thread below it), the
+//     lives in registers (a sliding window of primitives per thread, so
+//     every z face is computed once by the thread below it), the
 //     current plane with its x/y guard ring lives in LDS.
 //   * Guard cells are never stored: a tile load gathers them from the linked
 //     neighbour block's interior (or wraps / repeats the edge), so HBM holds
@@ -955,10 +956,10 @@ constexpr size_t stage_lds_bytes() {
   return a > b ? a : b;
 }
 
-// Occupancy: the mixed tile's LDS (41 KiB per workgroup) admits three
-// workgroups, i.e. three waves per SIMD.  Stage 2 holds Un and the CFL rate
-// on top of stage 1's registers and would settle at two; it is held to the
-// register budget of three waves (a few spilled dwords, measured faster).
+// Occupancy: registers bound the mixed tile to three waves per SIMD (its
+// 18.9 KiB of LDS would admit more).  Stage 2 holds Un and the CFL rate on top
+// of stage 1's registers and would settle at two; it is held to the register
+// budget of three waves (a few spilled dwords, measured faster).
 template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((MIXED && STAGE == 2) ? 3 : 1)))
 void k_stage(StageArgs A) {
