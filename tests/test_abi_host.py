@@ -147,3 +147,12 @@ def test_einfeldt_variant_passes_host_validation(prec):
         H.HostStream(m, _Host(m.arena_len), [range(0, 1), range(1, 2)], prec).close()
     except H.HydroError as e:
         assert e.code in (H.EDEVICE, H.ENOMEM), str(e)
+
+
+def test_extent_and_count_limits_rejected_on_host():
+    m = I.block_grid((1, 1, 1), (16392, 8, 2), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    rc, msg = _create(m)
+    assert rc == H.EINVAL and "16384" in msg, msg
+    descs = H.descs_from_mesh(good())
+    h = C.c_void_p()
+    assert H.lib().hydro_mesh_create(descs, 0, 3, FAKE_ARENA, 100, None, C.byref(h)) == H.EINVAL

@@ -12,7 +12,9 @@ tests), mixed FP32/FP64 L1(rho) <= 1e-5.
     layers are the whole neighbour;
   * a 2D mesh of non-square blocks;
   * a one-block self-periodic packet through the packet path and the graph
-    path.
+    path;
+  * supersonic flow, every x face on the upwind branch of HLLC;
+  * a block at the maximum x extent.
 """
 import numpy as np
 import pytest
@@ -128,3 +130,17 @@ def test_single_self_periodic_block_packet_and_graph():
             b = H.Batch([pk])
             b.run(5, CFL, GAMMA)
         assert rel_err(mesh, to_host(arena), R) <= 1e-12
+
+
+def test_supersonic_flow_every_face_upwind():
+    """Mach ~3.4 flow along x over a density wave: every x face takes the
+    upwind (left-state) branch of HLLC."""
+    mesh = I.block_grid((2, 1, 1), (16, 16, 8), (0, 0, 0), (1, 0.5, 0.25), "periodic", 3)
+    prims = I.grid_field(mesh, lambda x, y, z: (1.0 + 0.2 * np.sin(2 * np.pi * x), 4.0, 0.0, 0.0, 1.0))
+    check_both(mesh, I.conserved_arena(mesh, prims, GAMMA), 10)
+
+
+def test_widest_block_accepted():
+    """A block at the maximum x extent (16384 cells), eight rows, two planes."""
+    mesh = I.block_grid((1, 1, 1), (16384, 8, 2), (0, 0, 0), (1, 8.0 / 16384, 2.0 / 16384), "periodic", 3)
+    check_both(mesh, smooth_state(mesh), 3)
