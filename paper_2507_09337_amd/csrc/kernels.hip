@@ -407,7 +407,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   TileCtx C;
   tile_setup<TX, TY, DIM>(C, A, it, sub, lt, dt, PX);
   const int b = C.b;
-  const bool active = C.active;
+  const bool active = (NSUB == 1) ? true : C.active;  // a 16x16 item always names a block
   const DevBlock *__restrict__ Bp = C.Bp;
   const int x = C.x, y = C.y, z0 = C.z0, z1 = C.z1;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
@@ -670,7 +670,8 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 
   TileCtx C;
   tile_setup<TX, TX, DIM>(C, A, it, sub, lt, dt, PX);
-  const bool active = C.active;
+  // a 16x16 item always names a block: the flag is a constant there
+  const bool active = (NSUB == 1) ? true : C.active;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
   const float g32 = (float)gamma, rgm1 = (float)(1.0 / gm1);
   const double *__restrict__ src = A.src;
@@ -869,44 +870,32 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     dlo[v] = Wc[v] - Wb[v];
     zp[v] = Wb[v] + 0.5f * minmod_f(Wb[v] - Wa[v], dlo[v]);
   }
-  float fzlo[5] = {0, 0, 0, 0, 0};
-  for (int j = C.z0 - 1; j < C.z1; ++j) {
-    const bool work = j >= C.z0;
-    fetch_z(j + 2, Ud);
-    if (work) {
-      fetch_un(j, Un);
-      stage_plane(Wb, Gr);
-      if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
-      __syncthreads();
-      faces();
-    }
-    // z face j+1/2 (one site for every z face of the column)
+  // z face above plane j: primitives of plane j+2 (loaded one iteration
+  // earlier), then the minus state of plane j+1 and HLLC with the carried plus
+  // state of plane j
+  auto zface = [&](float (&fz)[5]) {
     if (active) prims(Ud, Wd, true);
-    float fz[5];
-    {
-      float zr[5];
+    float zr[5];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        const float dhi = Wd[v] - Wc[v];
-        const float m = minmod_f(dlo[v], dhi);
-        zr[v] = Wc[v] - 0.5f * m;
-        dlo[v] = dhi;
-        Wa[v] = Wc[v] + 0.5f * m;  // plus state of plane j+1, carried into zp below
-      }
-      const float Lr[5] = {zp[0], zp[3], zp[2], zp[1], zp[4]};
-      const float Rr[5] = {zr[0], zr[3], zr[2], zr[1], zr[4]};
-      float F[5];
-      hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
-      fz[0] = F[0];
-      fz[1] = F[3];
-      fz[2] = F[2];
-      fz[3] = F[1];
-      fz[4] = F[4];
+    for (int v = 0; v < NVAR; ++v) {
+      const float dhi = Wd[v] - Wc[v];
+      const float m = minmod_f(dlo[v], dhi);
+      zr[v] = Wc[v] - 0.5f * m;
+      dlo[v] = dhi;
+      Wa[v] = Wc[v] + 0.5f * m;  // plus state of plane j+1, carried into zp
     }
-    if (work) {
-      __syncthreads();
-      update(j, Ub, Un, fzlo, fz);
-    }
+    const float Lr[5] = {zp[0], zp[3], zp[2], zp[1], zp[4]};
+    const float Rr[5] = {zr[0], zr[3], zr[2], zr[1], zr[4]};
+    float F[5];
+    hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
+    fz[0] = F[0];
+    fz[1] = F[3];
+    fz[2] = F[2];
+    fz[3] = F[1];
+    fz[4] = F[4];
+  };
+  float fzlo[5];
+  auto rotate = [&](const float (&fz)[5]) {
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) {
       zp[v] = Wa[v];
@@ -916,6 +905,29 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       Ub[v] = Uc[v];
       Uc[v] = Ud[v];
     }
+  };
+  {  // the z face below the first plane
+    fetch_z(C.z0 + 1, Ud);
+    float fz[5];
+    zface(fz);
+    rotate(fz);
+  }
+  for (int j = C.z0; j < C.z1; ++j) {
+    fetch_z(j + 2, Ud);
+    fetch_un(j, Un);
+    stage_plane(Wb, Gr);
+    if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
+    __syncthreads();
+    // x and y faces, then the z face (register work, no LDS), then the
+    // leftover faces of job 2: one straight run of independent work
+    face(jw0, 1, jo0, true);
+    face(jw1, PX, jo1, false);
+    float fz[5];
+    zface(fz);
+    if (has2) face(jw2, x2 ? 1 : PX, jo2, x2);
+    __syncthreads();
+    update(j, Ub, Un, fzlo, fz);
+    rotate(fz);
   }
 }
 
