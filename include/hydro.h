@@ -183,7 +183,17 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * class the tiling is:
  *   tile:   0 = 16x16 tiles, one per 256-thread workgroup (needs n[0], n[1]
  *               multiples of 16); 1 = 8x8 tiles, four per workgroup;
+ *               2..4 = 16x16 tiles in z-runs: a workgroup takes the same
+ *               tile of that many consecutive blocks of a z column (blocks
+ *               linked along +z within the batch, whole blocks, 3D); the
+ *               mixed-precision tile marches through the run without
+ *               re-reading the z halo of each block;
  *   zchunk: z planes per work item (0 = the whole block; 3D only).
+ * Without a setting a class uses 16x16 tiles (8x8 if its extents need them)
+ * on whole blocks, in z-runs of two when the class has at least 96 x (number
+ * of CUs) 16x16 tiles (the shorter work list then still gives 16 rounds of
+ * resident workgroups).  get_config reports the tiling in effect (2..4 for
+ * z-runs, where the blocks' +z links allow them).
  * Per batch, grid = workgroups per stage launch (0 = one per work item; else a
  * persistent grid of that many workgroups looping over the work list), and
  * xcd_remap = 1 renumbers workgroups so that each of the GPU's 8 XCDs (each

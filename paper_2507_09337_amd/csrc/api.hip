@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -41,7 +42,8 @@ hydro_status fail(hydro_status s, const std::string &msg) {
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 struct TileCfg {
-  int tile = -1;   // -1: default (16x16 when the extents allow it)
+  int tile = -1;   // -1: default (16x16 when the extents allow it); 0: 16x16; 1: 8x8;
+                   // 2..4: 16x16 in runs of that many blocks along +z
   int zchunk = 0;  // 0: whole block
 };
 
@@ -172,8 +174,21 @@ DevBlock make_devblock(const hydro_block_desc *all, int b, int ndim) {
 }
 
 // ---------------------------------------------------------------- work lists
+// Default z-run length of a class of whole 16x16-tiled 3D blocks with
+// `tiles` tiles: two when the halved work list still gives 16 or more rounds
+// of resident workgroups (three per CU), so it costs no tail; else one.
+int default_run(const hydro_mesh *m, int64_t tiles) {
+  return (m->ndim == 3 && m->num_cu > 0 && tiles / 2 >= 16 * 3 * (int64_t)m->num_cu) ? 2 : 1;
+}
+
 // Items in block order; 8x8 tiles are packed four to an item (tiles of equal
-// z range only).
+// z range only).  Blocks of a class tiled in z-runs (3D, whole blocks) are
+// chained along their +z links within `ids` and cut into runs of k blocks;
+// one item then takes the same 16x16 tile of each block of a run in turn
+// (the default tiling uses runs of two on large classes; see run_len).
+// Run items are emitted level by level (the first run of every column, then
+// the second, ...), so the workgroups that run at the same time hold
+// neighbouring columns at the same height.
 void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
                  std::vector<WorkItem> &items, int &kmask) {
   items.clear();
@@ -198,11 +213,34 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
     items.push_back(it);
     kmask |= 2;
   };
+  auto cfg_of = [&](int32_t b) {
+    TileCfg c;
+    auto f = cfg.find(block_class(m->desc[b], m->ndim));
+    if (f != cfg.end()) c = f->second;
+    return c;
+  };
+  // 16x16 tiles per class among the listed blocks (for the default run length)
+  std::map<int, int64_t> class_tiles;
   for (int32_t b : ids) {
     const hydro_block_desc &d = m->desc[b];
-    TileCfg c;
-    auto f = cfg.find(block_class(d, m->ndim));
-    if (f != cfg.end()) c = f->second;
+    class_tiles[block_class(d, m->ndim)] += (int64_t)(d.n[0] / 16) * (d.n[1] / 16);
+  }
+  // run length of a block: > 1 only for whole-block 16x16 tiling in 3D
+  auto run_len = [&](int32_t b) {
+    const hydro_block_desc &d = m->desc[b];
+    const TileCfg c = cfg_of(b);
+    const bool can16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
+    if (m->ndim != 3 || !can16 || c.tile == 1 || c.tile == 0 || (c.zchunk > 0 && c.zchunk < d.n[2])) return 1;
+    if (c.tile < 0) return default_run(m, class_tiles[block_class(d, m->ndim)]);
+    return std::min(c.tile, 4);
+  };
+  std::unordered_map<int32_t, int> pos;  // position in ids of the blocks tiled in runs
+  for (int i = 0; i < (int)ids.size(); ++i)
+    if (run_len(ids[i]) > 1) pos[ids[i]] = i;
+  for (int32_t b : ids) {
+    if (pos.count(b)) continue;
+    const hydro_block_desc &d = m->desc[b];
+    const TileCfg c = cfg_of(b);
     const bool can16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
     const bool use16 = can16 && c.tile != 1;
     const int nz = d.n[2];
@@ -234,6 +272,67 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
   }
   for (auto &kv : pending)
     if (!kv.second.empty()) emit8(kv.second, kv.first.first, kv.first.second);
+  if (pos.empty()) return;
+
+  // z columns of the run-tiled blocks: b -> b' along +z when b' is b's +z
+  // neighbour, b is b''s -z neighbour, and both are run-tiled with equal
+  // extents and run length
+  std::vector<char> taken(ids.size(), 0);
+  auto link = [&](int32_t b, int f) -> int32_t {
+    const hydro_block_desc &d = m->desc[b];
+    if (d.face_kind[f] != HYDRO_NBR) return -1;
+    const int32_t o = d.nbr[f];
+    auto it = pos.find(o);
+    if (it == pos.end() || taken[it->second]) return -1;
+    const hydro_block_desc &e = m->desc[o];
+    if (e.face_kind[f ^ 1] != HYDRO_NBR || e.nbr[f ^ 1] != b) return -1;
+    if (e.n[0] != d.n[0] || e.n[1] != d.n[1] || e.n[2] != d.n[2] || run_len(o) != run_len(b)) return -1;
+    return o;
+  };
+  std::vector<std::vector<std::vector<int32_t>>> levels;  // level -> runs
+  for (int32_t b : ids) {
+    auto pb = pos.find(b);
+    if (pb == pos.end() || taken[pb->second]) continue;
+    // head of b's column: walk -z; on a cycle take the member first in ids
+    int32_t h = b, first = b;
+    for (int32_t p = link(h, 4); p >= 0; p = link(h, 4)) {
+      if (p == b) {
+        h = first;
+        break;
+      }
+      h = p;
+      if (pos[h] < pos[first]) first = h;
+    }
+    std::vector<int32_t> col;
+    for (int32_t c = h; c >= 0; c = link(c, 5)) {
+      col.push_back(c);
+      taken[pos[c]] = 1;
+    }
+    const size_t k = (size_t)run_len(b);
+    for (size_t r = 0; r * k < col.size(); ++r) {
+      if (levels.size() <= r) levels.resize(r + 1);
+      levels[r].emplace_back(col.begin() + r * k, col.begin() + std::min(col.size(), (r + 1) * k));
+    }
+  }
+  for (const auto &lv : levels)
+    for (const auto &run : lv) {
+      const hydro_block_desc &d = m->desc[run[0]];
+      for (int y0 = 0; y0 < d.n[1]; y0 += 16)
+        for (int x0 = 0; x0 < d.n[0]; x0 += 16) {
+          WorkItem it;
+          std::memset(&it, 0, sizeof(it));
+          it.kind = hyd::KIND_T16;
+          for (int s = 0; s < 4; ++s) {
+            it.block[s] = s < (int)run.size() ? run[s] : -1;
+            it.x0[s] = (int16_t)x0;
+            it.y0[s] = (int16_t)y0;
+          }
+          it.z0 = 0;
+          it.z1 = (int16_t)d.n[2];
+          items.push_back(it);
+          kmask |= 1;
+        }
+    }
 }
 
 hydro_status upload_items(const std::vector<WorkItem> &items, int kmask, WorkList &wl, hipStream_t s) {
@@ -923,9 +1022,10 @@ extern "C" {
 // ------------------------------------------------------------------ tuning
 hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
-  if (tile != 0 && tile != 1) return fail(HYDRO_EINVAL, "tile must be 0 (16x16) or 1 (8x8)");
+  if (tile < 0 || tile > 4) return fail(HYDRO_EINVAL, "tile must be 0 (16x16), 1 (8x8) or 2..4 (16x16 z-runs)");
   if (zchunk < 0) return fail(HYDRO_EINVAL, "zchunk must be >= 0");
-  if (tile == 0 && edge > 0 && edge % 16) return fail(HYDRO_EINVAL, "16x16 tiles need an edge multiple of 16");
+  if (tile != 1 && edge > 0 && edge % 16) return fail(HYDRO_EINVAL, "16x16 tiles need an edge multiple of 16");
+  if (tile >= 2 && zchunk != 0) return fail(HYDRO_EINVAL, "z-runs take whole blocks (zchunk 0)");
   TileCfg c;
   c.tile = tile;
   c.zchunk = zchunk;
@@ -950,10 +1050,11 @@ hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_re
 
 hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass) {
   if (!b || !out || !nclass || nclass_max < 0) return fail(HYDRO_EINVAL, "bad arguments");
-  std::map<int, int64_t> cells;
+  std::map<int, int64_t> cells, tiles;
   for (int id : b->ids) {
     const hydro_block_desc &d = b->m->desc[id];
     cells[block_class(d, b->m->ndim)] += (int64_t)d.n[0] * d.n[1] * d.n[2];
+    tiles[block_class(d, b->m->ndim)] += (int64_t)(d.n[0] / 16) * (d.n[1] / 16);
   }
   out[0] = b->grid;
   out[1] = b->remap;
@@ -971,7 +1072,14 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
         }
       const bool can16 = any && any->n[0] % 16 == 0 && any->n[1] % 16 == 0;
       out[2 + 4 * k + 0] = kv.first;
-      out[2 + 4 * k + 1] = (can16 && c.tile != 1) ? 0 : 1;
+      // the tiling in effect: 8x8, 16x16, or the z-run length
+      int tile = 1;
+      if (can16 && c.tile != 1) {
+        const bool whole = b->m->ndim == 3 && (c.zchunk == 0 || (any && c.zchunk >= any->n[2]));
+        const int run = !whole ? 1 : (c.tile < 0 ? default_run(b->m, tiles[kv.first]) : std::max(c.tile, 1));
+        tile = run > 1 ? run : 0;
+      }
+      out[2 + 4 * k + 1] = tile;
       out[2 + 4 * k + 2] = c.zchunk;
       out[2 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
     }
@@ -1066,6 +1174,12 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
         cands.push_back(c);
       }
     }
+    if (can16 && m->ndim == 3)
+      for (int k : {2, 4}) {
+        TileCfg c;
+        c.tile = k;
+        cands.push_back(c);
+      }
     // parity reference: default tiling on a sample of blocks
     std::vector<int32_t> sample(ids.begin(), ids.begin() + std::min<size_t>(ids.size(), 64));
     std::vector<double> ref, got;

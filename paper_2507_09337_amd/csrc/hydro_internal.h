@@ -27,9 +27,11 @@ struct DevBlock {
   int32_t pad[2];
 };
 
-// One work item of a stage launch: a column of x-y tiles marched over
-// z planes [z0, z1).  kind 0: one 16x16 tile (block[0]); kind 1: up to four
-// 8x8 tiles, one per 64-thread wave, from any blocks (block[s] < 0 = empty).
+// One work item of a stage launch: x-y tiles, each marched over z planes
+// [z0, z1).  kind 0: a run of up to four 16x16 tiles (block[s], x0[s],
+// y0[s]) taken one after the other by the whole workgroup, block[s] < 0
+// ending the run; kind 1: up to four 8x8 tiles, one per 64-thread wave, from
+// any blocks (block[s] < 0 = empty).
 struct WorkItem {
   int32_t block[4];
   int16_t x0[4];

@@ -388,7 +388,7 @@ __device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const
 // ------------------------------------------------------------------------
 template <int TX, int TY, int NSUB, int DIM, bool MIXED, int STAGE, int SPEEDS>
 __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
-                                         double dt, double &lam, int &bad, int &badblk) {
+                                         int slot, double dt, double &lam, int &bad, int &badblk) {
   using T = typename std::conditional<MIXED, float, double>::type;
   using G = TileGeom<TX, TY>;
   constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NXF = G::NXF, NYF = G::NYF;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   T *Fy = Fx + NVAR * NXF;                               // [5][TY+1][TX]
 
   TileCtx C;
-  tile_setup<TX, TY, DIM>(C, A, it, sub, lt, dt, PX);
+  tile_setup<TX, TY, DIM>(C, A, it, NSUB == 1 ? slot : sub, lt, dt, PX);
   const int b = C.b;
   const bool active = (NSUB == 1) ? true : C.active;  // a 16x16 item always names a block
   const DevBlock *__restrict__ Bp = C.Bp;
@@ -656,7 +656,7 @@ struct SplitGeom {
 
 template <int TX, int NSUB, int DIM, int STAGE, int SPEEDS>
 __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
-                                               double dt, double &lam, int &bad, int &badblk) {
+                                               int slot, double dt, double &lam, int &bad, int &badblk) {
   using G = SplitGeom<TX>;
   constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NF = G::NF;
   static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
@@ -669,7 +669,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   float *L = reinterpret_cast<float *>(lds) + sub * G::ELEMS;
 
   TileCtx C;
-  tile_setup<TX, TX, DIM>(C, A, it, sub, lt, dt, PX);
+  tile_setup<TX, TX, DIM>(C, A, it, NSUB == 1 ? slot : sub, lt, dt, PX);
   // a 16x16 item always names a block: the flag is a constant there
   const bool active = (NSUB == 1) ? true : C.active;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
@@ -841,12 +841,11 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   float Wa[5] = {1, 0, 0, 0, 1}, Wb[5] = {1, 0, 0, 0, 1}, Wc[5] = {1, 0, 0, 0, 1}, Wd[5] = {1, 0, 0, 0, 1};
   double Ub[5] = {0, 0, 0, 0, 0}, Uc[5] = {0, 0, 0, 0, 0}, Ud[5] = {0, 0, 0, 0, 0};
   // own cells: wave-uniform base per variable, 32-bit lane offset
-  const double *__restrict__ sb = src + C.boff;
-  const int plane32 = (int)C.plane, cidx32 = (int)C.cidx;
   auto fetch_z = [&](int z, double (&U)[5]) {
     if (!active) return;
     if (z >= 0 && z < C.nz) {
-      const int o = z * plane32 + cidx32;
+      const double *__restrict__ sb = src + C.boff;
+      const int o = z * (int)C.plane + (int)C.cidx;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) U[v] = sb[(int64_t)v * C.ncell + o];
     } else {
@@ -912,22 +911,36 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     zface(fz);
     rotate(fz);
   }
-  for (int j = C.z0; j < C.z1; ++j) {
-    fetch_z(j + 2, Ud);
-    fetch_un(j, Un);
-    stage_plane(Wb, Gr);
-    if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
-    __syncthreads();
-    // x and y faces, then the z face (register work, no LDS), then the
-    // leftover faces of job 2: one straight run of independent work
-    face(jw0, 1, jo0, true);
-    face(jw1, PX, jo1, false);
-    float fz[5];
-    zface(fz);
-    if (has2) face(jw2, x2 ? 1 : PX, jo2, x2);
-    __syncthreads();
-    update(j, Ub, Un, fzlo, fz);
-    rotate(fz);
+  // A 16x16 item may be a z-run: slots 1..3 name the blocks above slot 0's,
+  // linked along +z.  The plane loop then carries on from one block into the
+  // next: planes beyond a block are read through its +z link, which is the
+  // next block of the run, so the window already holds that block's first
+  // planes -- no new prologue and no z halo read twice.
+  int nrun = 1;
+  if (NSUB == 1)
+    while (nrun < 4 && __builtin_amdgcn_readfirstlane(it->block[nrun]) >= 0) ++nrun;
+  for (int s = 0; s < nrun; ++s) {
+    if (s > 0) {
+      tile_setup<TX, TX, DIM>(C, A, it, s, lt, dt, PX);
+      fetch_guard(C.z0, Gr);  // the new block's guard cells of its first plane
+    }
+    for (int j = C.z0; j < C.z1; ++j) {
+      fetch_z(j + 2, Ud);
+      fetch_un(j, Un);
+      stage_plane(Wb, Gr);
+      if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
+      __syncthreads();
+      // x and y faces, then the z face (register work, no LDS), then the
+      // leftover faces of job 2: one straight run of independent work
+      face(jw0, 1, jo0, true);
+      face(jw1, PX, jo1, false);
+      float fz[5];
+      zface(fz);
+      if (has2) face(jw2, x2 ? 1 : PX, jo2, x2);
+      __syncthreads();
+      update(j, Ub, Un, fzlo, fz);
+      rotate(fz);
+    }
   }
 }
 
@@ -988,16 +1001,26 @@ void k_stage(StageArgs A) {
   const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
   for (int i = first; i < A.nitems; i += gridDim.x) {
     const WorkItem *it = A.items + i;
-    if constexpr (MIXED) {
-      if ((KMASK & 1) && it->kind == KIND_T16)
-        run_tile_mixed<16, 1, DIM, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
-      else if (KMASK & 2)
-        run_tile_mixed<8, 4, DIM, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
-    } else {
-      if ((KMASK & 1) && it->kind == KIND_T16)
-        run_tile<16, 16, 1, DIM, false, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
-      else if (KMASK & 2)
-        run_tile<8, 8, 4, DIM, false, STAGE, SPEEDS>(A, it, lds, dt, lam, bad, badblk);
+    if ((KMASK & 1) && it->kind == KIND_T16) {
+      // a 16x16 item is a run of up to four tiles taken one after the other
+      // (the same tile of consecutive blocks of a z column: each tile's z
+      // halo planes were read moments before by this workgroup, from L2)
+      if constexpr (MIXED) {
+        run_tile_mixed<16, 1, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);  // marches the whole run
+      } else {
+        for (int s = 0; s < 4; ++s) {
+          if (s > 0) {
+            if (__builtin_amdgcn_readfirstlane(it->block[s]) < 0) break;
+            __syncthreads();  // LDS is reused by the next tile
+          }
+          run_tile<16, 16, 1, DIM, false, STAGE, SPEEDS>(A, it, lds, s, dt, lam, bad, badblk);
+        }
+      }
+    } else if (KMASK & 2) {
+      if constexpr (MIXED)
+        run_tile_mixed<8, 4, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
+      else
+        run_tile<8, 8, 4, DIM, false, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -1020,22 +1043,26 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
     const bool t16 = (KMASK & 1) && it->kind == KIND_T16;
     const int TX = t16 ? 16 : 8, NT = t16 ? 256 : 64;
     const int sub = __builtin_amdgcn_readfirstlane(threadIdx.x / NT), lt = threadIdx.x % NT;
-    const int b = __builtin_amdgcn_readfirstlane(it->block[sub]);
-    if (b < 0) continue;
-    const DevBlock &B = A.blocks[b];
-    const int x = __builtin_amdgcn_readfirstlane(it->x0[sub]) + lt % TX;
-    const int y = __builtin_amdgcn_readfirstlane(it->y0[sub]) + lt / TX;
-    const int64_t plane = (int64_t)B.n[0] * B.n[1];
-    const double *p = A.src + B.off + (int64_t)y * B.n[0] + x;
-    const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
-    for (int z = za; z < zb; ++z) {
-      double W[5];
-      if (!load_prim<false>(p + z * plane, B.ncell, gm1, W)) {
-        bad = 1;
-        badblk = min(badblk, b);
-        continue;
+    // the tiles of the item: slots 0..3 of a 16x16 run, or this wave's 8x8 tile
+    for (int s = 0; s < (t16 ? 4 : 1); ++s) {
+      const int slot = t16 ? s : sub;
+      const int b = __builtin_amdgcn_readfirstlane(it->block[slot]);
+      if (b < 0) break;
+      const DevBlock &B = A.blocks[b];
+      const int x = __builtin_amdgcn_readfirstlane(it->x0[slot]) + lt % TX;
+      const int y = __builtin_amdgcn_readfirstlane(it->y0[slot]) + lt / TX;
+      const int64_t plane = (int64_t)B.n[0] * B.n[1];
+      const double *p = A.src + B.off + (int64_t)y * B.n[0] + x;
+      const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
+      for (int z = za; z < zb; ++z) {
+        double W[5];
+        if (!load_prim<false>(p + z * plane, B.ncell, gm1, W)) {
+          bad = 1;
+          badblk = min(badblk, b);
+          continue;
+        }
+        lam = fmax(lam, cell_rate<DIM>(W, A.gamma, B.dx[0], B.dx[1], B.dx[2]));
       }
-      lam = fmax(lam, cell_rate<DIM>(W, A.gamma, B.dx[0], B.dx[1], B.dx[2]));
     }
   }
   flush_acc(A.acc, lam, bad, badblk, true);

@@ -141,7 +141,7 @@ def test_sedov_graph_fp64_conservation_and_mirror(sedov):
 
 
 # ------------------------------------------------------ C3 smooth (reduced)
-@pytest.mark.parametrize("tile,zchunk", [(0, 0), (1, 0), (0, 4)], ids=["t16", "t8", "t16-z4"])
+@pytest.mark.parametrize("tile,zchunk", [(0, 0), (1, 0), (0, 4), (3, 0)], ids=["t16", "t8", "t16-z4", "t16-run3"])
 def test_smooth_fp64_and_mixed(tile, zchunk):
     P = I.smooth3d(nblk=(4, 4, 4), nsteps=30)
     R, dts, t_ref = oracle_run(P, P.nsteps)
