@@ -642,6 +642,18 @@ __device__ __forceinline__ float minmod_f(float a, float b) {
 // their two-cell x/y guard ring [TX+4 rows][TX+4] (corners unused), then the
 // x fluxes (faces 0..TX-1 of each row [row][face], then face TX [row]) and
 // the y fluxes [face 0..TX][x].
+// A value that is the same on every lane of the wave, kept in scalar
+// registers (the compiler cannot see the uniformity through the loads).
+__device__ __forceinline__ double wave_uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)x), hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
 template <int TX>
 struct SplitGeom {
   static constexpr int NT = TX * TX;
@@ -670,6 +682,18 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 
   TileCtx C;
   tile_setup<TX, TX, DIM>(C, A, it, NSUB == 1 ? slot : sub, lt, dt, PX);
+  auto uniform_ctx = [&]() {
+  if (NSUB == 1) {  // one block per tile: its scalars are wave-uniform
+    C.boff = wave_uniform(C.boff);
+    C.plane = wave_uniform(C.plane);
+    C.ncell = __builtin_amdgcn_readfirstlane(C.ncell);
+    C.nz = __builtin_amdgcn_readfirstlane(C.nz);
+    C.dtdx = wave_uniform(C.dtdx);
+    C.dtdy = wave_uniform(C.dtdy);
+    C.dtdz = wave_uniform(C.dtdz);
+  }
+  };
+  uniform_ctx();
   // a 16x16 item always names a block: the flag is a constant there
   const bool active = (NSUB == 1) ? true : C.active;
   const double gamma = A.gamma, gm1 = gamma - 1.0;
@@ -774,7 +798,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     if (has2) face(jw2, x2 ? 1 : PX, jo2, x2);
   };
 
-  const double rdx0 = 1.0 / C.dx0, rdx1 = 1.0 / C.dx1, rdx2 = 1.0 / C.dx2;
+  const double rdx0 = wave_uniform(1.0 / C.dx0), rdx1 = wave_uniform(1.0 / C.dx1), rdx2 = wave_uniform(1.0 / C.dx2);
   // C) FP64 update of this thread's cell in plane z (FP32 fluxes widened);
   // Un is the prefetched stage-2 state of the cell
   auto update = [&](int z, const double (&Us)[5], const double (&Un)[5], const float (&fzlo)[5],
@@ -922,6 +946,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   for (int s = 0; s < nrun; ++s) {
     if (s > 0) {
       tile_setup<TX, TX, DIM>(C, A, it, s, lt, dt, PX);
+      uniform_ctx();
       fetch_guard(C.z0, Gr);  // the new block's guard cells of its first plane
     }
     for (int j = C.z0; j < C.z1; ++j) {
