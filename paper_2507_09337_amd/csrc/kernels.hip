@@ -46,13 +46,6 @@ template <typename T>
 struct Arith;
 
 template <>
-struct Arith<double> {  // IEEE division and square root
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-  static __device__ __forceinline__ double sound(double g, double p, double r) { return __builtin_sqrt(g * p / r); }
-};
-
-template <>
 struct Arith<float> {  // hardware reciprocal and reciprocal square root (about 1 ulp)
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -227,9 +220,7 @@ __device__ __forceinline__ bool recover_fast(double U0, double U1, double U2, do
   return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
 }
 
-template <bool FAST>
 __device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t vs, double gm1, double W[5]) {
-  if (FAST) return recover_fast(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
   return recover(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
 }
 
@@ -243,18 +234,6 @@ __device__ __forceinline__ double cell_rate(const double W[5], double gamma, dou
   lam += (fabs(W[2]) + c) / dx1;
   if (DIM == 3) lam += (fabs(W[3]) + c) / dx2;
   return lam;
-}
-
-// Face flux in the frame of direction d (normal velocity first), for either
-// precision.
-template <bool MIXED, int SPEEDS>
-__device__ __forceinline__ void face_flux(const typename std::conditional<MIXED, float, double>::type L[5],
-                                          const typename std::conditional<MIXED, float, double>::type R[5],
-                                          double gamma, typename std::conditional<MIXED, float, double>::type F[5]) {
-  if constexpr (MIXED)
-    hllc<float, SPEEDS>(L, R, (float)gamma, (float)(1.0 / (gamma - 1.0)), F);
-  else
-    hllc_fp64<SPEEDS>(L, R, gamma, F);
 }
 
 // Source of an out-of-block cell along one axis: face f's source block and
@@ -386,10 +365,10 @@ __device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const
 // One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
 // marched over z planes [z0, z1).
 // ------------------------------------------------------------------------
-template <int TX, int TY, int NSUB, int DIM, bool MIXED, int STAGE, int SPEEDS>
+template <int TX, int TY, int NSUB, int DIM, int STAGE, int SPEEDS>
 __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                          int slot, double dt, double &lam, int &bad, int &badblk) {
-  using T = typename std::conditional<MIXED, float, double>::type;
+  using T = double;
   using G = TileGeom<TX, TY>;
   constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NXF = G::NXF, NYF = G::NYF;
   static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
@@ -493,7 +472,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
       const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
       T Fr[5];
-      face_flux<MIXED, SPEEDS>(Lr, Rr, gamma, Fr);
+      hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
       out[0] = Fr[0];
       out[ostride] = isx ? Fr[1] : Fr[2];
       out[2 * ostride] = isx ? Fr[2] : Fr[1];
@@ -597,7 +576,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
       const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
       T Fr[5];
-      face_flux<MIXED, SPEEDS>(Lr, Rr, gamma, Fr);
+      hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
       fz[0] = Fr[0];
       fz[1] = Fr[3];
       fz[2] = Fr[2];
@@ -1007,11 +986,13 @@ constexpr size_t stage_lds_bytes() {
 }
 
 // Occupancy: registers bound the mixed tile to three waves per SIMD (its
-// 18.9 KiB of LDS would admit more).  Stage 2 holds Un and the CFL rate on top
-// of stage 1's registers and would settle at two; it is held to the register
-// budget of three waves (a few spilled dwords, measured faster).
+// 18.9 KiB of LDS would admit more).  Mixed stage 2 holds Un and the CFL rate
+// on top of stage 1's registers and would settle at two; it is held to the
+// register budget of three waves.  The FP64 tile's stage 1 (184 registers,
+// two waves) is held to three waves too: a few spilled dwords, measured 4 %
+// faster; its stage 2 spills too much at three and keeps two.
 template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((MIXED && STAGE == 2) ? 3 : 1)))
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((STAGE == 2) == MIXED ? 3 : 1)))
 void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1038,14 +1019,14 @@ void k_stage(StageArgs A) {
             if (__builtin_amdgcn_readfirstlane(it->block[s]) < 0) break;
             __syncthreads();  // LDS is reused by the next tile
           }
-          run_tile<16, 16, 1, DIM, false, STAGE, SPEEDS>(A, it, lds, s, dt, lam, bad, badblk);
+          run_tile<16, 16, 1, DIM, STAGE, SPEEDS>(A, it, lds, s, dt, lam, bad, badblk);
         }
       }
     } else if (KMASK & 2) {
       if constexpr (MIXED)
         run_tile_mixed<8, 4, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
       else
-        run_tile<8, 8, 4, DIM, false, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
+        run_tile<8, 8, 4, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -1081,7 +1062,7 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
       const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
       for (int z = za; z < zb; ++z) {
         double W[5];
-        if (!load_prim<false>(p + z * plane, B.ncell, gm1, W)) {
+        if (!load_prim(p + z * plane, B.ncell, gm1, W)) {
           bad = 1;
           badblk = min(badblk, b);
           continue;
