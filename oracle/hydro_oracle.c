@@ -64,7 +64,7 @@
 
 enum { ORACLE_NBR = 0, ORACLE_OUTFLOW = 1, ORACLE_PERIODIC_SELF = 2 };
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 3, ORACLE_ENONPHYS = 4 };
-enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1 };
+enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1, ORACLE_SPEEDS_PVRS = 2 };
 
 typedef struct {
   int32_t nblocks;
@@ -74,7 +74,7 @@ typedef struct {
   const int32_t *kind;   /* [nblocks][6] face kind for -x,+x,-y,+y,-z,+z */
   const int32_t *nbr;    /* [nblocks][6] neighbour block id of ORACLE_NBR faces */
   const int64_t *offset; /* [nblocks] element offset of variable 0 in the arena */
-  int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS or _EINFELDT */
+  int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS, _EINFELDT or _PVRS */
 } oracle_mesh;
 
 /* ------------------------------------------------------------------------ */
@@ -202,6 +202,13 @@ void oracle_plm_face(const double *w, double *wl, double *wr) {
  *     d_bar^2 = (s_L c_L^2 + s_R c_R^2) / (s_L + s_R) + eta2 (u_R - u_L)^2,
  *       eta2 = s_L s_R / (2 (s_L + s_R)^2),
  *     S_L = u_bar - d_bar, S_R = u_bar + d_bar.
+ *   Pressure-based (Toro 2009, sec. 10.5.2) with the primitive-variable
+ *   (PVRS) estimate of the star pressure:
+ *     p_pvrs = (p_L + p_R)/2 - (u_R - u_L) rho_bar c_bar / 2,
+ *       rho_bar = (rho_L + rho_R)/2, c_bar = (c_L + c_R)/2,  p* = max(0, p_pvrs);
+ *     q_K = 1 if p* <= p_K (a rarefaction: the acoustic speed), else the
+ *       shock factor q_K = sqrt(1 + (gamma + 1)/(2 gamma) (p* / p_K - 1));
+ *     S_L = u_L - c_L q_L, S_R = u_R + c_R q_R.
  */
 void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int speeds, double *S) {
   double rL = WL[0], uL = WL[1], pL = WL[4];
@@ -215,6 +222,15 @@ void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int sp
     double dbar = sqrt((sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * (uR - uL) * (uR - uL));
     S[0] = ubar - dbar;
     S[1] = ubar + dbar;
+  } else if (speeds == ORACLE_SPEEDS_PVRS) {
+    double rbar = 0.5 * (rL + rR), cbar = 0.5 * (cL + cR);
+    double ppv = 0.5 * (pL + pR) - 0.5 * (uR - uL) * rbar * cbar;
+    double ps = fmax(0.0, ppv);
+    double k = (gamma + 1.0) / (2.0 * gamma);
+    double qL = ps <= pL ? 1.0 : sqrt(1.0 + k * (ps / pL - 1.0));
+    double qR = ps <= pR ? 1.0 : sqrt(1.0 + k * (ps / pR - 1.0));
+    S[0] = uL - cL * qL;
+    S[1] = uR + cR * qR;
   } else {
     double SL = fmin(uL - cL, uR - cR);
     double SR = fmax(uL + cL, uR + cR);
@@ -228,7 +244,7 @@ void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int sp
  * (Toro 2009, sec. 10.4-10.6; Toro, Spruce & Speares 1994).
  * WL, WR = (rho, u_normal, u_t1, u_t2, p).  F = (mass, normal momentum,
  * t1 momentum, t2 momentum, energy) flux in the same frame.
- *   Wave speeds S_L, S_R: oracle_wave_speeds (Davis, or Einfeldt).
+ *   Wave speeds S_L, S_R: oracle_wave_speeds (Davis, Einfeldt or PVRS).
  *   Contact speed: S* = [p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)]
  *                       / [rho_L (S_L - u_L) - rho_R (S_R - u_R)].
  *   Star states:   U*_K = rho_K (S_K - u_K)/(S_K - S*) *
@@ -394,7 +410,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
 int oracle_validate(const oracle_mesh *m) {
   if (!m || m->nblocks < 0 || (m->ndim != 2 && m->ndim != 3)) return ORACLE_EINVAL;
   if (m->nblocks > 0 && (!m->n || !m->dx || !m->kind || !m->nbr || !m->offset)) return ORACLE_EINVAL;
-  if (m->speeds != ORACLE_SPEEDS_DAVIS && m->speeds != ORACLE_SPEEDS_EINFELDT) return ORACLE_EINVAL;
+  if (m->speeds < ORACLE_SPEEDS_DAVIS || m->speeds > ORACLE_SPEEDS_PVRS) return ORACLE_EINVAL;
   for (int b = 0; b < m->nblocks; ++b) {
     const int32_t *n = m->n + 3 * b;
     if (m->ndim == 2 && n[2] != 1) return ORACLE_EINVAL;

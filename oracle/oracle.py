@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libhydro_oracle.so")
 _OVERRIDE = os.environ.get("HYDRO_ORACLE_LIB")
 
 OK, EINVAL, ENOMEM, ENONPHYS = 0, 1, 3, 4
-DAVIS, EINFELDT = 0, 1  # HLLC wave-speed bounds
+DAVIS, EINFELDT, PVRS = 0, 1, 2  # HLLC wave-speed bounds
 
 
 class OracleError(RuntimeError):

@@ -14,7 +14,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
-PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py"]
+PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py",
+        "tests/test_oracle_pvrs.py"]
 
 MUTANTS = {
     "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
@@ -39,6 +40,11 @@ MUTANTS = {
     "einfeldt-unweighted-c2": ("(sL * cL * cL + sR * cR * cR) / (sL + sR)", "(cL * cL + cR * cR) / 2.0"),
     "einfeldt-step-uses-davis": ("oracle_hllc_speeds(rl, rr, gamma, m->speeds, f);",
                                  "oracle_hllc_speeds(rl, rr, gamma, ORACLE_SPEEDS_DAVIS, f);"),
+    "pvrs-jump-sign": ("0.5 * (pL + pR) - 0.5 * (uR - uL)", "0.5 * (pL + pR) + 0.5 * (uR - uL)"),
+    "pvrs-impedance-left-only": ("double rbar = 0.5 * (rL + rR)", "double rbar = rL"),
+    "pvrs-shock-factor": ("double k = (gamma + 1.0) / (2.0 * gamma);", "double k = (gamma - 1.0) / (2.0 * gamma);"),
+    "pvrs-branch-inverted": ("double qR = ps <= pR ? 1.0 :", "double qR = ps >= pR ? 1.0 :"),
+    "pvrs-right-uses-left-sound": ("S[1] = uR + cR * qR;", "S[1] = uR + cL * qR;"),
 }
 
 
