@@ -21,7 +21,8 @@
  * Reconstruction, Riemann solver and time-step rule are not given by the paper
  * and follow the textbook methods: PLM (van Leer 1979) on primitive variables
  * with minmod (Roe 1986); HLLC (Toro, Spruce & Speares 1994) with Davis
- * wave speeds; SSP-RK2 (Shu & Osher 1988); dt = CFL / max_c sum_d (|u_d|+c)/dx_d.
+ * wave speeds (Einfeldt or PVRS as variants); SSP-RK2 (Shu & Osher 1988);
+ * dt = CFL / max_c sum_d (|u_d|+c)/dx_d.
  *
  * Conventions for every call
  *   - Every call returns a hydro_status; HYDRO_OK is 0.  No exception or
@@ -69,10 +70,19 @@ typedef enum {
   HYDRO_FP32_FP64 = 1 /* FP64 state, recovery, accumulation and dt; PLM + HLLC in FP32   */
 } hydro_precision;
 
-/* Method variant, OR-ed into a precision code: HLLC with Einfeldt's wave-speed
- * bounds (sqrt(rho)-weighted mean normal velocity -+ d_bar, Toro sec. 10.5.1)
- * instead of Davis's min/max of u -+ c.  Without it the bounds are Davis's. */
+/* Method variants, at most one OR-ed into a precision code (both at once is
+ * EINVAL).  Without either, HLLC's wave-speed bounds are Davis's min/max of
+ * u -+ c.
+ * HYDRO_SPEEDS_EINFELDT: Einfeldt's bounds, the sqrt(rho)-weighted mean normal
+ *   velocity -+ d_bar (Toro sec. 10.5.1).
+ * HYDRO_SPEEDS_PVRS: pressure-based bounds u_L - c_L q_L, u_R + c_R q_R from
+ *   the primitive-variable linearised star pressure (Toro sec. 10.5.2): q_K is
+ *   1 on a rarefaction and the shock factor of that pressure otherwise.  The
+ *   linear pressure grows like the velocity jump, a strong shock's like its
+ *   square, so in a strong collision the bounds can cross; the method has no
+ *   guard against it (Toro pairs it with other estimates adaptively). */
 #define HYDRO_SPEEDS_EINFELDT 0x100
+#define HYDRO_SPEEDS_PVRS 0x200
 
 typedef enum {
   HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
@@ -117,7 +127,7 @@ hydro_status hydro_mesh_destroy(hydro_mesh *m);
 
 /* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
  * listed blocks of mesh m, advanced in the given hydro_precision (optionally
- * OR HYDRO_SPEEDS_EINFELDT).  block_ids:
+ * OR one HYDRO_SPEEDS_* variant).  block_ids:
  * host array of nblocks distinct ids.  Builds the packet's device work list.
  * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
  * EDEVICE. */

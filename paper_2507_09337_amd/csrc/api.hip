@@ -391,13 +391,14 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
 // A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
-// with HYDRO_SPEEDS_EINFELDT.
+// with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS.
 bool prec_valid(int32_t p) {
-  const int32_t base = p & 0xff;
-  return (p & ~(0xff | HYDRO_SPEEDS_EINFELDT)) == 0 && (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
+  const int32_t base = p & 0xff, var = p & ~0xff;
+  return (var == 0 || var == HYDRO_SPEEDS_EINFELDT || var == HYDRO_SPEEDS_PVRS) &&
+         (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
 }
 bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
-int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : 0; }
+int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : (p & HYDRO_SPEEDS_PVRS) ? 2 : 0; }
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a) {

@@ -5,7 +5,7 @@
 // halo, 2nd-order Runge-Kutta refreshing guards before each stage; Sec. 5.2:
 // ideal-gas gamma-law EOS).  Reconstruction and flux follow the textbook
 // methods named in include/hydro.h: PLM on primitives with minmod, HLLC with
-// Davis (or, as a variant, Einfeldt) wave speeds, SSP-RK2 combine, CFL rate
+// Davis (or, as variants, Einfeldt or PVRS) wave speeds, SSP-RK2 combine, CFL rate
 // sum_d (|u_d| + c)/dx_d.
 //
 // Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
@@ -75,12 +75,16 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
   r = w2 - T(0.5) * minmod(d12, d23);
 }
 
-enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1 };
+enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1, SPEEDS_PVRS = 2 };
 
 // HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).  Wave
 // speed bounds: Davis, min/max of u -+ c over both sides; or Einfeldt,
 // u_bar -+ d_bar with sqrt(rho)-weighted u_bar and d_bar^2 = weighted mean of
-// c^2 + s_L s_R / (2 (s_L + s_R)^2) (u_R - u_L)^2 (Toro sec. 10.5.1).
+// c^2 + s_L s_R / (2 (s_L + s_R)^2) (u_R - u_L)^2 (Toro sec. 10.5.1); or
+// pressure-based, u_L - c_L q_L and u_R + c_R q_R with q_K = 1 unless the
+// linearised (PVRS) star pressure p* = max(0, (p_L + p_R)/2 - (u_R - u_L)
+// rho_bar c_bar / 2) exceeds p_K, then the shock factor
+// sqrt(1 + (gamma + 1)/(2 gamma) (p*/p_K - 1)) (Toro sec. 10.5.2).
 // The side of the contact is chosen first (left if S_L >= 0 or S* >= 0) and
 // only that side's physical flux and star state are formed:
 //   F = F_K + S (U*_K - U_K),  S = min(S_L, 0) on the left, max(S_R, 0) on the
@@ -104,6 +108,19 @@ __device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T 
     const T d = d2 * __builtin_amdgcn_rsqf(d2);
     SL = ub - d;
     SR = ub + d;
+  } else if constexpr (SPEEDS == SPEEDS_PVRS) {
+    const T cL = A::sound(g, L[4], L[0]);
+    const T cR = A::sound(g, R[4], R[0]);
+    // rho_bar c_bar / 2 = (rho_L + rho_R)(c_L + c_R) / 8
+    const T ps = fmax(T(0.5) * (L[4] + R[4]) - T(0.125) * (R[1] - L[1]) * (L[0] + R[0]) * (cL + cR), T(0));
+    const T k = T(0.5) + T(0.5) * A::rcp(g);  // (gamma + 1)/(2 gamma)
+    // x_K = 1 + k (p*/p_K - 1) > 1 on the shock branch: q_K = x_K rsqrt(x_K)
+    const T xL = T(1) + k * (ps * A::rcp(L[4]) - T(1));
+    const T xR = T(1) + k * (ps * A::rcp(R[4]) - T(1));
+    const T qL = ps > L[4] ? xL * __builtin_amdgcn_rsqf(xL) : T(1);
+    const T qR = ps > R[4] ? xR * __builtin_amdgcn_rsqf(xR) : T(1);
+    SL = L[1] - cL * qL;
+    SR = R[1] + cR * qR;
   } else {
     const T cL = A::sound(g, L[4], L[0]);
     const T cR = A::sound(g, R[4], R[0]);
@@ -138,7 +155,7 @@ __device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T 
 }
 
 // HLLC in FP64 with the operations in the order of the textbook statement
-// (left and right states, Davis or Einfeldt speeds, S* from the jump relations, star state
+// (left and right states, Davis, Einfeldt or PVRS speeds, S* from the jump relations, star state
 // rho_K (S_K - u)/(S_K - S*) (1, S*, v, w, E/rho + (S* - u)(S* + p/(rho (S_K - u))))),
 // no contraction into FMAs.  Division and square root are IEEE-correct on the
 // device, so each face flux is rounded exactly as in a plain FP64 CPU
@@ -158,6 +175,14 @@ __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], 
     const double dbar = __builtin_sqrt((sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * (uR - uL) * (uR - uL));
     SL = ubar - dbar;
     SR = ubar + dbar;
+  } else if constexpr (SPEEDS == SPEEDS_PVRS) {
+    const double rbar = 0.5 * (rL + rR), cbar = 0.5 * (cL + cR);
+    const double ps = fmax(0.0, 0.5 * (pL + pR) - 0.5 * (uR - uL) * rbar * cbar);
+    const double k = (g + 1.0) / (2.0 * g);
+    const double qL = ps <= pL ? 1.0 : __builtin_sqrt(1.0 + k * (ps / pL - 1.0));
+    const double qR = ps <= pR ? 1.0 : __builtin_sqrt(1.0 + k * (ps / pR - 1.0));
+    SL = uL - cL * qL;
+    SR = uR + cR * qR;
   } else {
     SL = fmin(uL - cL, uR - cR);
     SR = fmax(uL + cL, uR + cR);
@@ -988,11 +1013,13 @@ constexpr size_t stage_lds_bytes() {
 // Occupancy: registers bound the mixed tile to three waves per SIMD (its
 // 18.9 KiB of LDS would admit more).  Mixed stage 2 holds Un and the CFL rate
 // on top of stage 1's registers and would settle at two; it is held to the
-// register budget of three waves.  The FP64 tile's stage 1 (184 registers,
-// two waves) is held to three waves too: a few spilled dwords, measured 4 %
-// faster; its stage 2 spills too much at three and keeps two.
+// register budget of three waves.  The FP64 16x16 tile's stage 1 (184
+// registers, two waves) is held to three waves too: a few spilled dwords,
+// measured 4 % faster; its stage 2, and both stages of kernels that also
+// carry the 8x8 tile, spill too much at three and keep two.
 template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu((STAGE == 2) == MIXED ? 3 : 1)))
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
+    (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1)) ? 3 : 1)))
 void k_stage(StageArgs A) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1113,8 +1140,14 @@ static hipError_t launch_ks(int kmask, int grid, hipStream_t s, const StageArgs 
 
 template <int DIM, bool MIXED, int STAGE>
 static hipError_t launch_k(int kmask, int speeds, int grid, hipStream_t s, const StageArgs &a) {
-  return speeds == SPEEDS_EINFELDT ? launch_ks<DIM, MIXED, STAGE, SPEEDS_EINFELDT>(kmask, grid, s, a)
-                                   : launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS>(kmask, grid, s, a);
+  switch (speeds) {
+    case SPEEDS_EINFELDT:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_EINFELDT>(kmask, grid, s, a);
+    case SPEEDS_PVRS:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_PVRS>(kmask, grid, s, a);
+    default:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS>(kmask, grid, s, a);
+  }
 }
 
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int grid, hipStream_t s,

@@ -126,7 +126,7 @@ def test_host_stream_rejects_bad_packets_on_host(case):
     assert e.value.code == H.EINVAL
 
 
-@pytest.mark.parametrize("prec", [2, 0x200, 0x101 | 0x1000, -1])
+@pytest.mark.parametrize("prec", [2, 0x400, 0x300, 0x301, 0x101 | 0x1000, -1])
 def test_bad_precision_codes_rejected_on_host(prec):
     m = I.independent_blocks([8, 8], 3)
     with pytest.raises(H.HydroError) as e:
@@ -134,9 +134,10 @@ def test_bad_precision_codes_rejected_on_host(prec):
     assert e.value.code == H.EINVAL and "precision" in str(e.value)
 
 
-@pytest.mark.parametrize("prec", [H.FP64 | H.EINFELDT, H.FP32_FP64 | H.EINFELDT])
-def test_einfeldt_variant_passes_host_validation(prec):
-    """A valid code with the wave-speed flag gets past every host check; with
+@pytest.mark.parametrize("prec", [H.FP64 | H.EINFELDT, H.FP32_FP64 | H.EINFELDT, H.FP64 | H.PVRS,
+                                  H.FP32_FP64 | H.PVRS])
+def test_wave_speed_variants_pass_host_validation(prec):
+    """A valid code with one wave-speed flag gets past every host check; with
     no GPU the first device call then fails loudly."""
     import torch
 

@@ -1,8 +1,8 @@
-"""GPU parity of the Einfeldt wave-speed variant (HYDRO_SPEEDS_EINFELDT)
-against the oracle run with the same bounds, through the C ABI: FP64 <= 1e-12
-relative per cell (floored), mixed L1(rho) <= 1e-5 on smooth flow; uniform
-states bitwise; conservation on a periodic blast; the host-resident packet
-path with the variant."""
+"""GPU parity of the HLLC wave-speed variants (HYDRO_SPEEDS_EINFELDT,
+HYDRO_SPEEDS_PVRS) against the oracle run with the same bounds, through the C
+ABI: FP64 <= 1e-12 relative per cell (floored), mixed L1(rho) <= 1e-5 on
+smooth flow; uniform states bitwise; conservation on a periodic blast; the
+host-resident packet path with each variant."""
 import math
 
 import numpy as np
@@ -15,7 +15,13 @@ from paper_2507_09337_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-EF = H.EINFELDT
+# (library flag, oracle option)
+VARIANTS = {"einfeldt": (H.EINFELDT, O.EINFELDT), "pvrs": (H.PVRS, O.PVRS)}
+
+
+@pytest.fixture(params=sorted(VARIANTS), scope="module")
+def variant(request):
+    return VARIANTS[request.param]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,16 +34,17 @@ def _gpu():
     yield
 
 
-def oracle_run(mesh, U0, nsteps, cfl, gamma):
+def oracle_run(mesh, U0, nsteps, cfl, gamma, speeds):
     R = U0.copy()
-    dts, t = O.run(mesh, R, nsteps, cfl, gamma, speeds=O.EINFELDT)
+    dts, t = O.run(mesh, R, nsteps, cfl, gamma, speeds=speeds)
     return R, dts, t
 
 
 @pytest.mark.parametrize("tile", [0, 1], ids=["t16", "t8"])
-def test_smooth_fp64_and_mixed(tile):
+def test_smooth_fp64_and_mixed(variant, tile):
+    EF, sp = variant
     P = I.smooth3d(nblk=(3, 3, 3), nsteps=15)
-    R, dts, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma)
+    R, dts, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
     for prec in (H.FP64, H.FP32_FP64):
         arena = to_dev(P.U0)
         mesh = H.Mesh(P.mesh, arena)
@@ -54,9 +61,10 @@ def test_smooth_fp64_and_mixed(tile):
         mesh.close()
 
 
-def test_sod2d_packet_path_fp64():
+def test_sod2d_packet_path_fp64(variant):
+    EF, sp = variant
     P = I.sod2d()
-    R, dts, _ = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma)
+    R, dts, _ = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
     arena = to_dev(P.U0)
     mesh = H.Mesh(P.mesh, arena)
     pk = H.Packet(mesh, range(P.mesh.nblocks), H.FP64 | EF)
@@ -67,13 +75,14 @@ def test_sod2d_packet_path_fp64():
     assert rel_err(P.mesh, to_host(arena), R) <= 1e-12
 
 
-def test_blast_plain_path_conservation():
+def test_blast_plain_path_conservation(variant):
+    EF, sp = variant
     gamma = 1.4
     m = I.block_grid((3, 3, 3), (16, 16, 16), (0, 0, 0), (1, 1, 1), "periodic", 3)
     prims = I.grid_field(m, lambda x, y, z: (1.0, 0.0, 0.0, 0.0, 1e-3))
     I.sedov_deposit(m, prims, 1.0, 2.0, (0.5, 0.5, 0.5), gamma)
     U0 = I.conserved_arena(m, prims, gamma)
-    R, dts, _ = oracle_run(m, U0, 10, 0.4, gamma)
+    R, dts, _ = oracle_run(m, U0, 10, 0.4, gamma, sp)
     arena = to_dev(U0)
     mesh = H.Mesh(m, arena)
     pks = [H.Packet(mesh, range(9 * k, 9 * k + 9), H.FP64 | EF) for k in range(3)]
@@ -92,7 +101,8 @@ def test_blast_plain_path_conservation():
 
 
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
-def test_uniform_state_bitwise(prec):
+def test_uniform_state_bitwise(variant, prec):
+    EF, _ = variant
     m = I.block_grid((2, 1, 2), (16, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
     U0 = I.uniform_state(m, gamma=1.4)
     arena = to_dev(U0)
@@ -102,11 +112,12 @@ def test_uniform_state_bitwise(prec):
     assert np.array_equal(to_host(arena), U0)
 
 
-def test_host_resident_packets():
+def test_host_resident_packets(variant):
     import torch
 
+    EF, sp = variant
     P = I.uneven(nblocks=40, nsteps=6)
-    R, _, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma)
+    R, _, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
     host = torch.from_numpy(P.U0.copy()).pin_memory()
     hs = H.HostStream(P.mesh, host, P.packets, H.FP64 | EF, 2)
     t = hs.run(P.nsteps, P.cfl, P.gamma)
