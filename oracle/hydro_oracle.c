@@ -22,11 +22,14 @@
  * The paper does not spell out the reconstruction, the Riemann solver or the
  * time-step rule.  This reference fixes them to named textbook methods:
  *   - PLM (van Leer 1979) on primitive variables (rho, u, v, w, p) with the
- *     minmod limiter (Roe 1986), one direction at a time, unsplit;
+ *     minmod limiter (Roe 1986), one direction at a time, unsplit; as a
+ *     method variant, PLM on the conserved variables with the face states
+ *     recovered afterwards;
  *   - HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; Toro,
  *     "Riemann Solvers and Numerical Methods for Fluid Dynamics", 3rd ed.,
- *     ch. 10) with Davis (1988) wave-speed bounds, or, as a method variant,
- *     Einfeldt's (1988) bounds from Roe-weighted averages (Toro sec. 10.5.1);
+ *     ch. 10) with Davis (1988) wave-speed bounds, or, as method variants,
+ *     Einfeldt's (1988) bounds from Roe-weighted averages (Toro sec. 10.5.1)
+ *     or pressure-based bounds (Toro sec. 10.5.2);
  *   - SSP-RK2 / TVD-RK2 (Shu & Osher 1988):
  *         U1   = Un + dt L(Un)
  *         Un+1 = 0.5 Un + 0.5 (U1 + dt L(U1));
@@ -39,7 +42,8 @@
  * interior layers), periodic on the block itself (wrap), or outflow
  * (zero-gradient copy of the first interior layer into both guard layers).
  * No floors: a non-positive density or pressure, or a non-finite value, in a
- * recovered state is an error (ORACLE_ENONPHYS).
+ * recovered state (a cell's, or with conserved reconstruction a face
+ * state's) is an error (ORACLE_ENONPHYS).
  *
  * Build: -O2 -ffp-contract=off -fno-fast-math, so every operation is rounded
  * as written.  OpenMP runs blocks of one stage in parallel; every block's
@@ -65,6 +69,7 @@
 enum { ORACLE_NBR = 0, ORACLE_OUTFLOW = 1, ORACLE_PERIODIC_SELF = 2 };
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 3, ORACLE_ENONPHYS = 4 };
 enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1, ORACLE_SPEEDS_PVRS = 2 };
+enum { ORACLE_RECON_PRIMITIVE = 0, ORACLE_RECON_CONSERVED = 1 };
 
 typedef struct {
   int32_t nblocks;
@@ -75,6 +80,7 @@ typedef struct {
   const int32_t *nbr;    /* [nblocks][6] neighbour block id of ORACLE_NBR faces */
   const int64_t *offset; /* [nblocks] element offset of variable 0 in the arena */
   int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS, _EINFELDT or _PVRS */
+  int32_t recon;         /* PLM variables: ORACLE_RECON_PRIMITIVE or _CONSERVED */
 } oracle_mesh;
 
 /* ------------------------------------------------------------------------ */
@@ -190,6 +196,34 @@ void oracle_plm_face(const double *w, double *wl, double *wr) {
     wl[v] = w1 + 0.5 * oracle_minmod(w1 - w0, w2 - w1);
     wr[v] = w2 - 0.5 * oracle_minmod(w2 - w1, w3 - w2);
   }
+}
+
+/* Primitive face states at the face between cells 1 and 2 of four
+ * consecutive cells given by their conserved values u[0..3] ([4][NVAR]).
+ * Every cell's primitives are recovered first (a non-physical cell is an
+ * error).  Then PLM runs on the variables `recon` names:
+ *   ORACLE_RECON_PRIMITIVE: on the recovered (rho, u, v, w, p);
+ *   ORACLE_RECON_CONSERVED: on (rho, rho u, rho v, rho w, E) themselves
+ *     (van Leer's MUSCL on the conserved variables), after which the two face
+ *     states are recovered with the same formulas; a non-physical face state
+ *     (rho <= 0, p <= 0, non-finite) is an error as well.
+ * Returns ORACLE_OK or ORACLE_ENONPHYS. */
+int oracle_face_states(const double *u, double gamma, int recon, double *wl, double *wr) {
+  double w[4][NVAR];
+  for (int s = 0; s < 4; ++s) {
+    oracle_prim(u + s * NVAR, gamma, w[s]);
+    if (!prim_ok(w[s])) return ORACLE_ENONPHYS;
+  }
+  if (recon == ORACLE_RECON_CONSERVED) {
+    double ul[NVAR], ur[NVAR];
+    oracle_plm_face(u, ul, ur);
+    oracle_prim(ul, gamma, wl);
+    oracle_prim(ur, gamma, wr);
+    if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;
+  } else {
+    oracle_plm_face(&w[0][0], wl, wr);
+  }
+  return ORACLE_OK;
 }
 
 /*
@@ -338,18 +372,15 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
     for (int k = 0; k < fn[2] && rc == ORACLE_OK; ++k)
       for (int j = 0; j < fn[1] && rc == ORACLE_OK; ++j)
         for (int i = 0; i < fn[0] && rc == ORACLE_OK; ++i) {
-          double w[4][NVAR];
+          double u[4][NVAR];
           for (int s = 0; s < 4; ++s) {
             int c[3] = {i, j, k};
             c[d] += s - 2; /* cells f-2, f-1, f, f+1 */
-            double u[NVAR];
-            for (int v = 0; v < NVAR; ++v) u[v] = S.q[pidx(&S, v, c[0], c[1], c[2])];
-            oracle_prim(u, gamma, w[s]);
-            if (!prim_ok(w[s])) rc = ORACLE_ENONPHYS;
+            for (int v = 0; v < NVAR; ++v) u[s][v] = S.q[pidx(&S, v, c[0], c[1], c[2])];
           }
-          if (rc) break;
           double wl[NVAR], wr[NVAR], rl[NVAR], rr[NVAR], f[NVAR];
-          oracle_plm_face(&w[0][0], wl, wr);
+          rc = oracle_face_states(&u[0][0], gamma, m->recon, wl, wr);
+          if (rc) break;
           /* rotate: the normal velocity component goes into slot 1 */
           for (int v = 0; v < NVAR; ++v) {
             rl[v] = wl[v];
@@ -411,6 +442,7 @@ int oracle_validate(const oracle_mesh *m) {
   if (!m || m->nblocks < 0 || (m->ndim != 2 && m->ndim != 3)) return ORACLE_EINVAL;
   if (m->nblocks > 0 && (!m->n || !m->dx || !m->kind || !m->nbr || !m->offset)) return ORACLE_EINVAL;
   if (m->speeds < ORACLE_SPEEDS_DAVIS || m->speeds > ORACLE_SPEEDS_PVRS) return ORACLE_EINVAL;
+  if (m->recon != ORACLE_RECON_PRIMITIVE && m->recon != ORACLE_RECON_CONSERVED) return ORACLE_EINVAL;
   for (int b = 0; b < m->nblocks; ++b) {
     const int32_t *n = m->n + 3 * b;
     if (m->ndim == 2 && n[2] != 1) return ORACLE_EINVAL;

@@ -23,6 +23,7 @@ _OVERRIDE = os.environ.get("HYDRO_ORACLE_LIB")
 
 OK, EINVAL, ENOMEM, ENONPHYS = 0, 1, 3, 4
 DAVIS, EINFELDT, PVRS = 0, 1, 2  # HLLC wave-speed bounds
+PRIMITIVE, CONSERVED = 0, 1  # variables PLM reconstructs
 
 
 class OracleError(RuntimeError):
@@ -41,6 +42,7 @@ class _Mesh(C.Structure):
         ("nbr", C.POINTER(C.c_int32)),
         ("offset", C.POINTER(C.c_int64)),
         ("speeds", C.c_int32),
+        ("recon", C.c_int32),
     ]
 
 
@@ -60,6 +62,7 @@ def lib():
         L.oracle_minmod.argtypes = [C.c_double, C.c_double]
         L.oracle_minmod.restype = C.c_double
         L.oracle_plm_face.argtypes = [dp, dp, dp]
+        L.oracle_face_states.argtypes = [dp, C.c_double, C.c_int, dp, dp]
         L.oracle_hllc.argtypes = [dp, dp, C.c_double, dp]
         L.oracle_hllc_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
         L.oracle_wave_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
@@ -82,7 +85,7 @@ def _dptr(a: np.ndarray):
 class _MeshArgs:
     """Keeps the contiguous copies alive while the C struct points at them."""
 
-    def __init__(self, mesh, speeds: int = DAVIS):
+    def __init__(self, mesh, speeds: int = DAVIS, recon: int = PRIMITIVE):
         self.n = np.ascontiguousarray(mesh.n, dtype=np.int32)
         self.dx = np.ascontiguousarray(mesh.dx, dtype=np.float64)
         self.kind = np.ascontiguousarray(mesh.kind, dtype=np.int32)
@@ -97,6 +100,7 @@ class _MeshArgs:
             self.nbr.ctypes.data_as(C.POINTER(C.c_int32)),
             self.offset.ctypes.data_as(C.POINTER(C.c_int64)),
             int(speeds),
+            int(recon),
         )
 
     def ref(self):
@@ -127,6 +131,16 @@ def plm_face(w4) -> tuple[np.ndarray, np.ndarray]:
     return wl, wr
 
 
+def face_states(u4, gamma: float, recon: int = PRIMITIVE):
+    """Primitive face states between cells 1 and 2 of four cells given by
+    their conserved values ([4][5]); (wl, wr), or None if a cell or (with
+    conserved reconstruction) a face state is non-physical."""
+    u = np.ascontiguousarray(u4, dtype=np.float64).reshape(4, 5)
+    wl, wr = np.empty(5), np.empty(5)
+    rc = lib().oracle_face_states(_dptr(u), gamma, int(recon), _dptr(wl), _dptr(wr))
+    return None if rc == ENONPHYS else (wl, wr)
+
+
 def hllc(WL, WR, gamma: float, speeds: int = DAVIS) -> np.ndarray:
     """HLLC flux for states (rho, u_normal, u_t1, u_t2, p)."""
     a = np.ascontiguousarray(WL, dtype=np.float64)
@@ -149,8 +163,8 @@ def wave_speeds(WL, WR, gamma: float, speeds: int = DAVIS) -> tuple[float, float
 
 
 # ------------------------------------------------------------------- mesh
-def validate(mesh, speeds: int = DAVIS) -> int:
-    m = _MeshArgs(mesh, speeds)
+def validate(mesh, speeds: int = DAVIS, recon: int = PRIMITIVE) -> int:
+    m = _MeshArgs(mesh, speeds, recon)
     return lib().oracle_validate(m.ref())
 
 
@@ -165,16 +179,17 @@ def dt(mesh, U: np.ndarray, gamma: float, cfl: float) -> float:
     return cfl / max_lambda(mesh, U, gamma)
 
 
-def step(mesh, U: np.ndarray, dt_: float, gamma: float, speeds: int = DAVIS) -> None:
+def step(mesh, U: np.ndarray, dt_: float, gamma: float, speeds: int = DAVIS, recon: int = PRIMITIVE) -> None:
     """One SSP-RK2 step of the whole mesh, in place."""
-    m = _MeshArgs(mesh, speeds)
+    m = _MeshArgs(mesh, speeds, recon)
     _check(lib().oracle_step(m.ref(), _dptr(U), dt_, gamma), "step")
 
 
-def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: int = DAVIS) -> np.ndarray:
+def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: int = DAVIS,
+                recon: int = PRIMITIVE) -> np.ndarray:
     """One step for the listed blocks; returns a copy of U whose target blocks
     hold the new state (other blocks unchanged)."""
-    m = _MeshArgs(mesh, speeds)
+    m = _MeshArgs(mesh, speeds, recon)
     t = np.ascontiguousarray(targets, dtype=np.int32)
     out = U.copy()
     _check(lib().oracle_step_subset(m.ref(), _dptr(U), dt_, gamma, t.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -183,9 +198,9 @@ def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: 
 
 
 def run(mesh, U: np.ndarray, nsteps: int, cfl: float, gamma: float, fixed_dt: float = 0.0,
-        speeds: int = DAVIS):
+        speeds: int = DAVIS, recon: int = PRIMITIVE):
     """nsteps steps in place; returns (dts array, t)."""
-    m = _MeshArgs(mesh, speeds)
+    m = _MeshArgs(mesh, speeds, recon)
     dts = np.zeros(max(nsteps, 1))
     t = C.c_double(0.0)
     _check(lib().oracle_run(m.ref(), _dptr(U), int(nsteps), cfl, gamma, fixed_dt, _dptr(dts), C.byref(t)), "run")

@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
 PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py",
-        "tests/test_oracle_pvrs.py"]
+        "tests/test_oracle_pvrs.py", "tests/test_oracle_recon.py"]
 
 MUTANTS = {
     "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
@@ -45,6 +45,11 @@ MUTANTS = {
     "pvrs-shock-factor": ("double k = (gamma + 1.0) / (2.0 * gamma);", "double k = (gamma - 1.0) / (2.0 * gamma);"),
     "pvrs-branch-inverted": ("double qR = ps <= pR ? 1.0 :", "double qR = ps >= pR ? 1.0 :"),
     "pvrs-right-uses-left-sound": ("S[1] = uR + cR * qR;", "S[1] = uR + cL * qR;"),
+    "recon-conserved-uses-primitives": ("    oracle_plm_face(u, ul, ur);", "    oracle_plm_face(&w[0][0], ul, ur);"),
+    "recon-no-face-state-check": ("if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;", "(void)0;"),
+    "recon-right-state-from-left": ("    oracle_prim(ur, gamma, wr);", "    oracle_prim(ul, gamma, wr);"),
+    "recon-option-ignored": ("oracle_face_states(&u[0][0], gamma, m->recon, wl, wr);",
+                             "oracle_face_states(&u[0][0], gamma, ORACLE_RECON_PRIMITIVE, wl, wr);"),
 }
 
 
