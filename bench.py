@@ -316,10 +316,12 @@ def main():
                                             for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
 
-    # method variants (Einfeldt, PVRS wave speeds): kernel time of a few eager steps
+    # method variants (Einfeldt, PVRS wave speeds; conserved reconstruction):
+    # kernel time of a few eager steps
     variants = {}
     for name, prec in (("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT), ("fp64_einfeldt", H.FP64 | H.EINFELDT),
-                       ("mixed_pvrs", H.FP32_FP64 | H.PVRS), ("fp64_pvrs", H.FP64 | H.PVRS)):
+                       ("mixed_pvrs", H.FP32_FP64 | H.PVRS), ("fp64_pvrs", H.FP64 | H.PVRS),
+                       ("mixed_conserved", H.FP32_FP64 | H.CONSERVED), ("fp64_conserved", H.FP64 | H.CONSERVED)):
         arena.copy_(U0_dev)
         b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
         k = b.time_kernels(min(args.steps, 5), P.cfl, P.gamma)
@@ -377,8 +379,8 @@ def main():
     km = kernel_ms["batched_mixed"]
     stage_ms = km["stage1_ms"] + km["stage2_ms"]
     achieved = BYTES_PER_CELL_UPDATE * cells / (stage_ms * 1e-3) / 1e9
-    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0>(hyd::StageArgs)",
-                                "void hyd::k_stage<3, true, 2, 1, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
+    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0, 0>(hyd::StageArgs)",
+                                "void hyd::k_stage<3, true, 2, 1, 0, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,

@@ -21,7 +21,8 @@
  * Reconstruction, Riemann solver and time-step rule are not given by the paper
  * and follow the textbook methods: PLM (van Leer 1979) on primitive variables
  * with minmod (Roe 1986); HLLC (Toro, Spruce & Speares 1994) with Davis
- * wave speeds (Einfeldt or PVRS as variants); SSP-RK2 (Shu & Osher 1988);
+ * wave speeds (Einfeldt or PVRS as variants; PLM on conserved variables as a
+ * further variant); SSP-RK2 (Shu & Osher 1988);
  * dt = CFL / max_c sum_d (|u_d|+c)/dx_d.
  *
  * Conventions for every call
@@ -84,6 +85,15 @@ typedef enum {
 #define HYDRO_SPEEDS_EINFELDT 0x100
 #define HYDRO_SPEEDS_PVRS 0x200
 
+/* Reconstruction variant, OR-ed into a precision code (with or without a
+ * wave-speed variant): PLM with minmod on the conserved variables (rho, rho u,
+ * rho v, rho w, E) instead of the primitives; the two face states are then
+ * recovered to primitives (in the reconstruction's precision: FP64, or FP32 in
+ * the mixed path) for HLLC.  A face state with rho <= 0 or p <= 0 is
+ * non-physical like a cell (HYDRO_ENONPHYS): velocity shear at low pressure
+ * produces one, where primitive reconstruction keeps p > 0. */
+#define HYDRO_RECON_CONSERVED 0x400
+
 typedef enum {
   HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
   HYDRO_OUTFLOW = 1,      /* zero gradient: both guard layers copy the edge layer        */
@@ -127,7 +137,7 @@ hydro_status hydro_mesh_destroy(hydro_mesh *m);
 
 /* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
  * listed blocks of mesh m, advanced in the given hydro_precision (optionally
- * OR one HYDRO_SPEEDS_* variant).  block_ids:
+ * OR at most one HYDRO_SPEEDS_* variant and HYDRO_RECON_CONSERVED).  block_ids:
  * host array of nblocks distinct ids.  Builds the packet's device work list.
  * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
  * EDEVICE. */

@@ -391,18 +391,22 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
 // A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
-// with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS.
+// with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS and with
+// HYDRO_RECON_CONSERVED.
 bool prec_valid(int32_t p) {
-  const int32_t base = p & 0xff, var = p & ~0xff;
-  return (var == 0 || var == HYDRO_SPEEDS_EINFELDT || var == HYDRO_SPEEDS_PVRS) &&
+  const int32_t base = p & 0xff, sp = p & (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS);
+  const int32_t rest = p & ~(0xff | HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS | HYDRO_RECON_CONSERVED);
+  return rest == 0 && sp != (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS) &&
          (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
 }
 bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
 int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : (p & HYDRO_SPEEDS_PVRS) ? 2 : 0; }
+int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : 0; }
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a) {
-  hipError_t e = hyd::launch_stage(m->ndim, is_mixed(prec), stage, wl.kmask, speeds_of(prec), grid_of(wl, grid), s, a);
+  hipError_t e = hyd::launch_stage(m->ndim, is_mixed(prec), stage, wl.kmask, speeds_of(prec), recon_of(prec),
+                                   grid_of(wl, grid), s, a);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return HYDRO_OK;
 }
@@ -992,10 +996,10 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
         good = good && ok(hipStreamWaitEvent(sl.stream, s->ready, 0));
         waited[k] = 1;
       }
-      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 1, s->wl[p].kmask, speeds_of(prec),
-                                          s->wl[p].nitems, sl.stream, slot_args(s, sl, s->wl[p], 1, gamma)));
-      good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), 2, s->wl[p].kmask, speeds_of(prec),
-                                          s->wl[p].nitems, sl.stream, slot_args(s, sl, s->wl[p], 2, gamma)));
+      for (int stage = 1; stage <= 2; ++stage)
+        good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), stage, s->wl[p].kmask, speeds_of(prec),
+                                            recon_of(prec), s->wl[p].nitems, sl.stream,
+                                            slot_args(s, sl, s->wl[p], stage, gamma)));
       if (p == lastp[k]) done(sl);
       good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
                                        hipMemcpyDeviceToHost, sl.stream));

@@ -68,7 +68,8 @@ struct StageArgs {
 
 // kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
 // speeds: 0 = Davis, 1 = Einfeldt, 2 = pressure-based (PVRS) wave-speed bounds in HLLC.
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int grid, hipStream_t s,
+// recon: 0 = PLM on primitives, 1 = PLM on conserved variables.
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,
                         const StageArgs &a);
 hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a);
 hipError_t launch_reset(DevTime *t, hipStream_t s);

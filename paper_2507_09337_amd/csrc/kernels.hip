@@ -4,9 +4,10 @@
 // Method (arXiv 2507.09337, Sec. 6: explicit finite volume with a guard-cell
 // halo, 2nd-order Runge-Kutta refreshing guards before each stage; Sec. 5.2:
 // ideal-gas gamma-law EOS).  Reconstruction and flux follow the textbook
-// methods named in include/hydro.h: PLM on primitives with minmod, HLLC with
-// Davis (or, as variants, Einfeldt or PVRS) wave speeds, SSP-RK2 combine, CFL rate
-// sum_d (|u_d| + c)/dx_d.
+// methods named in include/hydro.h: PLM on primitives with minmod (or, as a
+// variant, on the conserved variables with the face states recovered
+// afterwards), HLLC with Davis (or, as variants, Einfeldt or PVRS) wave
+// speeds, SSP-RK2 combine, CFL rate sum_d (|u_d| + c)/dx_d.
 //
 // Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
 //   * One workgroup = 256 threads = one x-y tile of a block (16x16) or four
@@ -76,6 +77,8 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
 }
 
 enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1, SPEEDS_PVRS = 2 };
+// Variables PLM reconstructs.
+enum { RECON_PRIMITIVE = 0, RECON_CONSERVED = 1 };
 
 // HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).  Wave
 // speed bounds: Davis, min/max of u -+ c over both sides; or Einfeldt,
@@ -92,66 +95,70 @@ enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1, SPEEDS_PVRS = 2 };
 // The star state is written with one reciprocal of (S_K - S*):
 //   q = (S_K - u)/(S_K - S*), rho* = rho q,
 //   E* = q E + rho* (S* - u) S* + (S* - u) p /(S_K - S*).
-template <typename T, int SPEEDS>
-__device__ __forceinline__ void hllc(const T L[5], const T R[5], T g, T rgm1, T F[5]) {
-  using A = Arith<T>;
-  T SL, SR;
+// FP32 arithmetic is not contracted by the compiler here: every fused
+// multiply-add is written out, so each inlined copy (one per face site)
+// rounds alike and identical states give identical fluxes at every site.
+template <int SPEEDS>
+__device__ __forceinline__ void hllc(const float L[5], const float R[5], float g, float rgm1, float F[5]) {
+#pragma clang fp contract(off)
+  using A = Arith<float>;
+  float SL, SR;
   if constexpr (SPEEDS == SPEEDS_EINFELDT) {
     // Einfeldt: u_bar -+ d_bar with sqrt(rho) weights s_K; c_K^2 = g p_K / rho_K = g p_K (1/s_K)^2
-    const T qL = __builtin_amdgcn_rsqf(L[0]), qR = __builtin_amdgcn_rsqf(R[0]);
-    const T sL = L[0] * qL, sR = R[0] * qR;
-    const T c2L = g * L[4] * qL * qL, c2R = g * R[4] * qR * qR;
-    const T is = A::rcp(sL + sR);
-    const T ub = (sL * L[1] + sR * R[1]) * is;
-    const T du = R[1] - L[1];
-    const T d2 = (sL * c2L + sR * c2R) * is + T(0.5) * sL * sR * is * is * du * du;
-    const T d = d2 * __builtin_amdgcn_rsqf(d2);
+    const float qL = __builtin_amdgcn_rsqf(L[0]), qR = __builtin_amdgcn_rsqf(R[0]);
+    const float sL = L[0] * qL, sR = R[0] * qR;
+    const float c2L = g * L[4] * qL * qL, c2R = g * R[4] * qR * qR;
+    const float is = A::rcp(sL + sR);
+    const float ub = __builtin_fmaf(sL, L[1], sR * R[1]) * is;
+    const float du = R[1] - L[1];
+    const float d2 = __builtin_fmaf(__builtin_fmaf(sL, c2L, sR * c2R), is, 0.5f * sL * sR * is * is * du * du);
+    const float d = d2 * __builtin_amdgcn_rsqf(d2);
     SL = ub - d;
     SR = ub + d;
   } else if constexpr (SPEEDS == SPEEDS_PVRS) {
-    const T cL = A::sound(g, L[4], L[0]);
-    const T cR = A::sound(g, R[4], R[0]);
+    const float cL = A::sound(g, L[4], L[0]);
+    const float cR = A::sound(g, R[4], R[0]);
     // rho_bar c_bar / 2 = (rho_L + rho_R)(c_L + c_R) / 8
-    const T ps = fmax(T(0.5) * (L[4] + R[4]) - T(0.125) * (R[1] - L[1]) * (L[0] + R[0]) * (cL + cR), T(0));
-    const T k = T(0.5) + T(0.5) * A::rcp(g);  // (gamma + 1)/(2 gamma)
+    const float ps = fmax(__builtin_fmaf(-0.125f * (R[1] - L[1]) * (L[0] + R[0]), cL + cR, 0.5f * (L[4] + R[4])), 0.0f);
+    const float k = __builtin_fmaf(0.5f, A::rcp(g), 0.5f);  // (gamma + 1)/(2 gamma)
     // x_K = 1 + k (p*/p_K - 1) > 1 on the shock branch: q_K = x_K rsqrt(x_K)
-    const T xL = T(1) + k * (ps * A::rcp(L[4]) - T(1));
-    const T xR = T(1) + k * (ps * A::rcp(R[4]) - T(1));
-    const T qL = ps > L[4] ? xL * __builtin_amdgcn_rsqf(xL) : T(1);
-    const T qR = ps > R[4] ? xR * __builtin_amdgcn_rsqf(xR) : T(1);
-    SL = L[1] - cL * qL;
-    SR = R[1] + cR * qR;
+    const float xL = __builtin_fmaf(k, __builtin_fmaf(ps, A::rcp(L[4]), -1.0f), 1.0f);
+    const float xR = __builtin_fmaf(k, __builtin_fmaf(ps, A::rcp(R[4]), -1.0f), 1.0f);
+    const float qL = ps > L[4] ? xL * __builtin_amdgcn_rsqf(xL) : 1.0f;
+    const float qR = ps > R[4] ? xR * __builtin_amdgcn_rsqf(xR) : 1.0f;
+    SL = __builtin_fmaf(-cL, qL, L[1]);
+    SR = __builtin_fmaf(cR, qR, R[1]);
   } else {
-    const T cL = A::sound(g, L[4], L[0]);
-    const T cR = A::sound(g, R[4], R[0]);
+    const float cL = A::sound(g, L[4], L[0]);
+    const float cR = A::sound(g, R[4], R[0]);
     SL = fmin(L[1] - cL, R[1] - cR);
     SR = fmax(L[1] + cL, R[1] + cR);
   }
-  const T aL = L[0] * (SL - L[1]);
-  const T aR = R[0] * (SR - R[1]);
-  const T Ss = A::div(R[4] - L[4] + aL * L[1] - aR * R[1], aL - aR);
-  const bool useL = (SL >= T(0)) || (Ss >= T(0));
-  const T r = useL ? L[0] : R[0];
-  const T u = useL ? L[1] : R[1];
-  const T v = useL ? L[2] : R[2];
-  const T w = useL ? L[3] : R[3];
-  const T p = useL ? L[4] : R[4];
-  const T SK = useL ? SL : SR;
-  const T S = useL ? fmin(SL, T(0)) : fmax(SR, T(0));
-  const T ru = r * u;
-  const T E = p * rgm1 + T(0.5) * r * (u * u + v * v + w * w);
-  const T f0 = ru, f1 = ru * u + p, f2 = ru * v, f3 = ru * w, f4 = u * (E + p);
-  const T inv = A::rcp(SK - Ss);
-  const T q = (SK - u) * inv;
-  const T a = r * q;
-  const T su = Ss - u;
-  const T Es = q * E + a * su * Ss + su * p * inv;
-  const bool star = (S != T(0));
-  F[0] = star ? f0 + S * (a - r) : f0;
-  F[1] = star ? f1 + S * (a * Ss - ru) : f1;
-  F[2] = star ? f2 + S * (v * (a - r)) : f2;
-  F[3] = star ? f3 + S * (w * (a - r)) : f3;
-  F[4] = star ? f4 + S * (Es - E) : f4;
+  const float aL = L[0] * (SL - L[1]);
+  const float aR = R[0] * (SR - R[1]);
+  const float Ss = A::div(__builtin_fmaf(-aR, R[1], __builtin_fmaf(aL, L[1], R[4] - L[4])), aL - aR);
+  const bool useL = (SL >= 0.0f) || (Ss >= 0.0f);
+  const float r = useL ? L[0] : R[0];
+  const float u = useL ? L[1] : R[1];
+  const float v = useL ? L[2] : R[2];
+  const float w = useL ? L[3] : R[3];
+  const float p = useL ? L[4] : R[4];
+  const float SK = useL ? SL : SR;
+  const float S = useL ? fmin(SL, 0.0f) : fmax(SR, 0.0f);
+  const float ru = r * u;
+  const float E = __builtin_fmaf(p, rgm1, (0.5f * r) * __builtin_fmaf(u, u, __builtin_fmaf(v, v, w * w)));
+  const float f0 = ru, f1 = __builtin_fmaf(ru, u, p), f2 = ru * v, f3 = ru * w, f4 = u * (E + p);
+  const float inv = A::rcp(SK - Ss);
+  const float q = (SK - u) * inv;
+  const float a = r * q;
+  const float su = Ss - u;
+  const float Es = __builtin_fmaf(q, E, __builtin_fmaf(a * su, Ss, su * p * inv));
+  const bool star = (S != 0.0f);
+  F[0] = star ? __builtin_fmaf(S, a - r, f0) : f0;
+  F[1] = star ? __builtin_fmaf(S, __builtin_fmaf(a, Ss, -ru), f1) : f1;
+  F[2] = star ? __builtin_fmaf(S, v * (a - r), f2) : f2;
+  F[3] = star ? __builtin_fmaf(S, w * (a - r), f3) : f3;
+  F[4] = star ? __builtin_fmaf(S, Es - E, f4) : f4;
 }
 
 // HLLC in FP64 with the operations in the order of the textbook statement
@@ -232,9 +239,10 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // are rounded to FP32 right after, while rho e = E - m.u/2 keeps FP64.
 __device__ __forceinline__ bool recover_fast(double U0, double U1, double U2, double U3, double U4, double gm1,
                                              double W[5]) {
+#pragma clang fp contract(off)
   const double inv = rcp_nr(U0);
   const double u = U1 * inv, v = U2 * inv, w = U3 * inv;
-  const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
+  const double rhoe = __builtin_fma(-0.5, __builtin_fma(U1, u, __builtin_fma(U2, v, U3 * w)), U4);
   const double p = gm1 * rhoe;
   W[0] = U0;
   W[1] = u;
@@ -390,7 +398,7 @@ __device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const
 // One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
 // marched over z planes [z0, z1).
 // ------------------------------------------------------------------------
-template <int TX, int TY, int NSUB, int DIM, int STAGE, int SPEEDS>
+template <int TX, int TY, int NSUB, int DIM, int STAGE, int SPEEDS, int RECON>
 __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                          int slot, double dt, double &lam, int &bad, int &badblk) {
   using T = double;
@@ -433,6 +441,9 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) U[v] = p[v * vs];
   };
+  // the variables PLM reconstructs (primitives, or the conserved values
+  // themselves); the cell's primitives are recovered either way, as the
+  // check for a non-physical cell
   auto prims = [&](const double (&U)[5], T (&W)[5], bool own) {
     double Wd[5];
     if (!recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
@@ -440,7 +451,20 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       if (own) badblk = min(badblk, b);
     }
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) W[v] = (T)Wd[v];
+    for (int v = 0; v < NVAR; ++v) W[v] = (RECON == RECON_CONSERVED) ? U[v] : Wd[v];
+  };
+  // conserved reconstruction: recover a face state (same formulas, FP64),
+  // which must be physical too
+  auto face_prims = [&](T (&s)[5]) {
+    if constexpr (RECON == RECON_CONSERVED) {
+      double Wd[5];
+      if (!recover(s[0], s[1], s[2], s[3], s[4], gm1, Wd) && active) {
+        bad = 1;
+        badblk = min(badblk, b);
+      }
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) s[v] = Wd[v];
+    }
   };
   auto fetch_guard = [&](int z, double (&G)[5]) {
     if (gslot >= 0) fetch(src + goff + (int64_t)z * gps, gvs, G);
@@ -494,6 +518,8 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
         const T *p = Wp + v * PP + base;
         plm(p[0], p[stride], p[2 * stride], p[3 * stride], wl[v], wr[v]);
       }
+      face_prims(wl);
+      face_prims(wr);
       const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
       const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
       T Fr[5];
@@ -598,6 +624,8 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
       T wl[5], wr[5];
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) plm(Wa[v], Wb[v], Wc[v], Wd[v], wl[v], wr[v]);
+      face_prims(wl);
+      face_prims(wr);
       const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
       const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
       T Fr[5];
@@ -670,9 +698,13 @@ struct SplitGeom {
   static constexpr int ELEMS = OFY + NVAR * NF;
 };
 
-template <int TX, int NSUB, int DIM, int STAGE, int SPEEDS>
+template <int TX, int NSUB, int DIM, int STAGE, int SPEEDS, int RECON>
 __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                                int slot, double dt, double &lam, int &bad, int &badblk) {
+  // No automatic contraction: the fused operations are written out, so the
+  // face code inlined at each face site rounds alike (a uniform state stays
+  // fixed bitwise) and the result does not hinge on the compiler's choices.
+#pragma clang fp contract(off)
   using G = SplitGeom<TX>;
   constexpr int NT = G::NT, PX = G::PX, PP = G::PP, NF = G::NF;
   static_assert(NT * NSUB == WG, "tile threads must fill the workgroup");
@@ -744,6 +776,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) U[v] = p[v * vs];
   };
+  // the variables PLM reconstructs, rounded to FP32: the primitives, or the
+  // conserved values themselves; the cell is recovered in FP64 either way,
+  // as the check for a non-physical cell
   auto prims = [&](const double (&U)[5], float (&W)[5], bool own) {
     double Wd[5];
     if (!recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
@@ -751,7 +786,28 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       if (own) badblk = min(badblk, C.b);
     }
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) W[v] = (float)Wd[v];
+    for (int v = 0; v < NVAR; ++v) W[v] = (float)((RECON == RECON_CONSERVED) ? U[v] : Wd[v]);
+  };
+  // conserved reconstruction: recover a face state in FP32 (the precision of
+  // the reconstruction), which must be physical too.  The fused operations are
+  // spelled out so that every face site rounds alike (identical states must
+  // give identical fluxes for a uniform state to stay fixed bitwise).
+  const float gm1f = (float)gm1;
+  auto face_prims = [&](float (&s)[5]) {
+    if constexpr (RECON == RECON_CONSERVED) {
+      const float inv = __builtin_amdgcn_rcpf(s[0]);
+      const float u = s[1] * inv, v = s[2] * inv, w = s[3] * inv;
+      const float ke = __builtin_fmaf(s[1], u, __builtin_fmaf(s[2], v, s[3] * w));
+      const float p = gm1f * __builtin_fmaf(-0.5f, ke, s[4]);
+      if (!(s[0] > 0.0f && p > 0.0f) && active) {  // a NaN fails both tests
+        bad = 1;
+        badblk = min(badblk, C.b);
+      }
+      s[1] = u;
+      s[2] = v;
+      s[3] = w;
+      s[4] = p;
+    }
   };
   auto fetch_guard = [&](int z, double (&G)[5]) {
     if (C.gslot >= 0) fetch(src + C.goff + (int64_t)z * C.gps, C.gvs, G);
@@ -782,13 +838,15 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       const float *w = L + v * PP + wb;
       const float w0 = w[0], w1 = w[st], w2 = w[2 * st], w3 = w[3 * st];
       const float d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
-      a[v] = w1 + 0.5f * minmod_f(d01, d12);
-      r[v] = w2 - 0.5f * minmod_f(d12, d23);
+      a[v] = __builtin_fmaf(0.5f, minmod_f(d01, d12), w1);
+      r[v] = __builtin_fmaf(-0.5f, minmod_f(d12, d23), w2);
     }
+    face_prims(a);
+    face_prims(r);
     const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
     const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
     float F[5];
-    hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
+    hllc<SPEEDS>(Lr, Rr, g32, rgm1, F);
     float *q = L + o;
     q[0] = F[0];
     q[NF] = isx ? F[1] : F[2];
@@ -815,9 +873,9 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       const float *fx = L + G::OFX + v * NF;
       const float *fy = L + G::OFY + v * NF + tj * TX + ti;
       double dU = C.dtdx * ((double)fx[tj * TX + ti] - (double)fx[fx1]);
-      dU += C.dtdy * ((double)fy[0] - (double)fy[TX]);
-      if (DIM == 3) dU += C.dtdz * ((double)fzlo[v] - (double)fzhi[v]);
-      Unew[v] = (STAGE == 1) ? Us[v] + dU : 0.5 * Un[v] + 0.5 * (Us[v] + dU);
+      dU = __builtin_fma(C.dtdy, (double)fy[0] - (double)fy[TX], dU);
+      if (DIM == 3) dU = __builtin_fma(C.dtdz, (double)fzlo[v] - (double)fzhi[v], dU);
+      Unew[v] = (STAGE == 1) ? Us[v] + dU : __builtin_fma(0.5, Un[v], 0.5 * (Us[v] + dU));
       // streamed out: the stage result is not read again in this launch, so it
       // must not evict the neighbours' cells that the guard reads hit in L2
       __builtin_nontemporal_store(Unew[v], &(A.dst + C.boff)[(int64_t)v * C.ncell + (int)c]);
@@ -832,8 +890,8 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
         double y = __builtin_amdgcn_rsq(q);
         y = y * __builtin_fma(-0.5 * q * y, y, 1.5);
         const double cs = gp * y;
-        double l = (fabs(W[1]) + cs) * rdx0 + (fabs(W[2]) + cs) * rdx1;
-        if (DIM == 3) l += (fabs(W[3]) + cs) * rdx2;
+        double l = __builtin_fma(fabs(W[1]) + cs, rdx0, (fabs(W[2]) + cs) * rdx1);
+        if (DIM == 3) l = __builtin_fma(fabs(W[3]) + cs, rdx2, l);
         lam = fmax(lam, l);
       }
     }
@@ -895,7 +953,7 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) {
     dlo[v] = Wc[v] - Wb[v];
-    zp[v] = Wb[v] + 0.5f * minmod_f(Wb[v] - Wa[v], dlo[v]);
+    zp[v] = __builtin_fmaf(0.5f, minmod_f(Wb[v] - Wa[v], dlo[v]), Wb[v]);
   }
   // z face above plane j: primitives of plane j+2 (loaded one iteration
   // earlier), then the minus state of plane j+1 and HLLC with the carried plus
@@ -907,14 +965,17 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     for (int v = 0; v < NVAR; ++v) {
       const float dhi = Wd[v] - Wc[v];
       const float m = minmod_f(dlo[v], dhi);
-      zr[v] = Wc[v] - 0.5f * m;
+      zr[v] = __builtin_fmaf(-0.5f, m, Wc[v]);
       dlo[v] = dhi;
-      Wa[v] = Wc[v] + 0.5f * m;  // plus state of plane j+1, carried into zp
+      Wa[v] = __builtin_fmaf(0.5f, m, Wc[v]);  // plus state of plane j+1, carried into zp
     }
-    const float Lr[5] = {zp[0], zp[3], zp[2], zp[1], zp[4]};
+    float zl[5] = {zp[0], zp[1], zp[2], zp[3], zp[4]};  // zp is carried on as it is
+    face_prims(zl);
+    face_prims(zr);
+    const float Lr[5] = {zl[0], zl[3], zl[2], zl[1], zl[4]};
     const float Rr[5] = {zr[0], zr[3], zr[2], zr[1], zr[4]};
     float F[5];
-    hllc<float, SPEEDS>(Lr, Rr, g32, rgm1, F);
+    hllc<SPEEDS>(Lr, Rr, g32, rgm1, F);
     fz[0] = F[0];
     fz[1] = F[3];
     fz[2] = F[2];
@@ -1017,7 +1078,7 @@ constexpr size_t stage_lds_bytes() {
 // registers, two waves) is held to three waves too: a few spilled dwords,
 // measured 4 % faster; its stage 2, and both stages of kernels that also
 // carry the 8x8 tile, spill too much at three and keep two.
-template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS>
+template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
     (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1)) ? 3 : 1)))
 void k_stage(StageArgs A) {
@@ -1039,28 +1100,30 @@ void k_stage(StageArgs A) {
       // (the same tile of consecutive blocks of a z column: each tile's z
       // halo planes were read moments before by this workgroup, from L2)
       if constexpr (MIXED) {
-        run_tile_mixed<16, 1, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);  // marches the whole run
+        run_tile_mixed<16, 1, DIM, STAGE, SPEEDS, RECON>(A, it, lds, 0, dt, lam, bad, badblk);  // marches the whole run
       } else {
         for (int s = 0; s < 4; ++s) {
           if (s > 0) {
             if (__builtin_amdgcn_readfirstlane(it->block[s]) < 0) break;
             __syncthreads();  // LDS is reused by the next tile
           }
-          run_tile<16, 16, 1, DIM, STAGE, SPEEDS>(A, it, lds, s, dt, lam, bad, badblk);
+          run_tile<16, 16, 1, DIM, STAGE, SPEEDS, RECON>(A, it, lds, s, dt, lam, bad, badblk);
         }
       }
     } else if (KMASK & 2) {
       if constexpr (MIXED)
-        run_tile_mixed<8, 4, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
+        run_tile_mixed<8, 4, DIM, STAGE, SPEEDS, RECON>(A, it, lds, 0, dt, lam, bad, badblk);
       else
-        run_tile<8, 8, 4, DIM, STAGE, SPEEDS>(A, it, lds, 0, dt, lam, bad, badblk);
+        run_tile<8, 8, 4, DIM, STAGE, SPEEDS, RECON>(A, it, lds, 0, dt, lam, bad, badblk);
     }
     __syncthreads();  // LDS is reused by the next item
   }
   // Stage 1 reports nothing: a bad Un was already reported by the rate
   // reduction that produced dt, and a bad U1 is caught when stage 2 recovers
-  // it.  (In the plain path stage 1 also clears the accumulator, so it must
-  // not race with its own reports.)
+  // it -- also after a non-physical face state of conserved reconstruction,
+  // whose negative pressure turns the face's sound speed, flux and so the
+  // cells' U1 into NaN.  (In the plain path stage 1 also clears the
+  // accumulator, so it must not race with its own reports.)
   if (STAGE == 2) flush_acc(A.acc, lam, bad, badblk, true);
 }
 
@@ -1122,44 +1185,51 @@ __global__ void k_finalize(DevTime *t, double cfl, int init) {
 // ------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------
-template <int DIM, bool MIXED, int STAGE, int SPEEDS>
+template <int DIM, bool MIXED, int STAGE, int SPEEDS, int RECON>
 static hipError_t launch_ks(int kmask, int grid, hipStream_t s, const StageArgs &a) {
   switch (kmask) {
     case 1:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
       break;
   }
   return hipGetLastError();
 }
 
-template <int DIM, bool MIXED, int STAGE>
-static hipError_t launch_k(int kmask, int speeds, int grid, hipStream_t s, const StageArgs &a) {
+template <int DIM, bool MIXED, int STAGE, int RECON>
+static hipError_t launch_kr(int kmask, int speeds, int grid, hipStream_t s, const StageArgs &a) {
   switch (speeds) {
     case SPEEDS_EINFELDT:
-      return launch_ks<DIM, MIXED, STAGE, SPEEDS_EINFELDT>(kmask, grid, s, a);
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_EINFELDT, RECON>(kmask, grid, s, a);
     case SPEEDS_PVRS:
-      return launch_ks<DIM, MIXED, STAGE, SPEEDS_PVRS>(kmask, grid, s, a);
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_PVRS, RECON>(kmask, grid, s, a);
     default:
-      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS>(kmask, grid, s, a);
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS, RECON>(kmask, grid, s, a);
   }
 }
 
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int grid, hipStream_t s,
+template <int DIM, bool MIXED, int STAGE>
+static hipError_t launch_k(int kmask, int speeds, int recon, int grid, hipStream_t s, const StageArgs &a) {
+  return recon == RECON_CONSERVED ? launch_kr<DIM, MIXED, STAGE, RECON_CONSERVED>(kmask, speeds, grid, s, a)
+                                  : launch_kr<DIM, MIXED, STAGE, RECON_PRIMITIVE>(kmask, speeds, grid, s, a);
+}
+
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,
                         const StageArgs &a) {
   if (grid <= 0) return hipSuccess;
-  const int k = kmask, w = speeds;
+  const int k = kmask, w = speeds, r = recon;
   if (ndim == 2) {
-    if (mixed) return stage == 1 ? launch_k<2, true, 1>(k, w, grid, s, a) : launch_k<2, true, 2>(k, w, grid, s, a);
-    return stage == 1 ? launch_k<2, false, 1>(k, w, grid, s, a) : launch_k<2, false, 2>(k, w, grid, s, a);
+    if (mixed)
+      return stage == 1 ? launch_k<2, true, 1>(k, w, r, grid, s, a) : launch_k<2, true, 2>(k, w, r, grid, s, a);
+    return stage == 1 ? launch_k<2, false, 1>(k, w, r, grid, s, a) : launch_k<2, false, 2>(k, w, r, grid, s, a);
   }
-  if (mixed) return stage == 1 ? launch_k<3, true, 1>(k, w, grid, s, a) : launch_k<3, true, 2>(k, w, grid, s, a);
-  return stage == 1 ? launch_k<3, false, 1>(k, w, grid, s, a) : launch_k<3, false, 2>(k, w, grid, s, a);
+  if (mixed) return stage == 1 ? launch_k<3, true, 1>(k, w, r, grid, s, a) : launch_k<3, true, 2>(k, w, r, grid, s, a);
+  return stage == 1 ? launch_k<3, false, 1>(k, w, r, grid, s, a) : launch_k<3, false, 2>(k, w, r, grid, s, a);
 }
 
 hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a) {

@@ -1,8 +1,10 @@
-"""GPU parity of the HLLC wave-speed variants (HYDRO_SPEEDS_EINFELDT,
-HYDRO_SPEEDS_PVRS) against the oracle run with the same bounds, through the C
-ABI: FP64 <= 1e-12 relative per cell (floored), mixed L1(rho) <= 1e-5 on
-smooth flow; uniform states bitwise; conservation on a periodic blast; the
-host-resident packet path with each variant."""
+"""GPU parity of the method variants -- HLLC wave-speed bounds
+(HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS) and PLM on conserved variables
+(HYDRO_RECON_CONSERVED, alone and with Einfeldt bounds) -- against the oracle
+run with the same options, through the C ABI: FP64 <= 1e-12 relative per cell
+(floored), mixed L1(rho) <= 1e-5 on smooth flow; uniform states bitwise;
+conservation on a periodic blast; the host-resident packet path with each
+variant; a non-physical face state of conserved reconstruction reported."""
 import math
 
 import numpy as np
@@ -15,8 +17,13 @@ from paper_2507_09337_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-# (library flag, oracle option)
-VARIANTS = {"einfeldt": (H.EINFELDT, O.EINFELDT), "pvrs": (H.PVRS, O.PVRS)}
+# (library flags, oracle options)
+VARIANTS = {
+    "einfeldt": (H.EINFELDT, dict(speeds=O.EINFELDT)),
+    "pvrs": (H.PVRS, dict(speeds=O.PVRS)),
+    "conserved": (H.CONSERVED, dict(recon=O.CONSERVED)),
+    "conserved-einfeldt": (H.CONSERVED | H.EINFELDT, dict(speeds=O.EINFELDT, recon=O.CONSERVED)),
+}
 
 
 @pytest.fixture(params=sorted(VARIANTS), scope="module")
@@ -34,17 +41,17 @@ def _gpu():
     yield
 
 
-def oracle_run(mesh, U0, nsteps, cfl, gamma, speeds):
+def oracle_run(mesh, U0, nsteps, cfl, gamma, opts):
     R = U0.copy()
-    dts, t = O.run(mesh, R, nsteps, cfl, gamma, speeds=speeds)
+    dts, t = O.run(mesh, R, nsteps, cfl, gamma, **opts)
     return R, dts, t
 
 
 @pytest.mark.parametrize("tile", [0, 1], ids=["t16", "t8"])
 def test_smooth_fp64_and_mixed(variant, tile):
-    EF, sp = variant
+    EF, opts = variant
     P = I.smooth3d(nblk=(3, 3, 3), nsteps=15)
-    R, dts, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
+    R, dts, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, opts)
     for prec in (H.FP64, H.FP32_FP64):
         arena = to_dev(P.U0)
         mesh = H.Mesh(P.mesh, arena)
@@ -62,9 +69,9 @@ def test_smooth_fp64_and_mixed(variant, tile):
 
 
 def test_sod2d_packet_path_fp64(variant):
-    EF, sp = variant
+    EF, opts = variant
     P = I.sod2d()
-    R, dts, _ = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
+    R, dts, _ = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, opts)
     arena = to_dev(P.U0)
     mesh = H.Mesh(P.mesh, arena)
     pk = H.Packet(mesh, range(P.mesh.nblocks), H.FP64 | EF)
@@ -76,13 +83,13 @@ def test_sod2d_packet_path_fp64(variant):
 
 
 def test_blast_plain_path_conservation(variant):
-    EF, sp = variant
+    EF, opts = variant
     gamma = 1.4
     m = I.block_grid((3, 3, 3), (16, 16, 16), (0, 0, 0), (1, 1, 1), "periodic", 3)
     prims = I.grid_field(m, lambda x, y, z: (1.0, 0.0, 0.0, 0.0, 1e-3))
     I.sedov_deposit(m, prims, 1.0, 2.0, (0.5, 0.5, 0.5), gamma)
     U0 = I.conserved_arena(m, prims, gamma)
-    R, dts, _ = oracle_run(m, U0, 10, 0.4, gamma, sp)
+    R, dts, _ = oracle_run(m, U0, 10, 0.4, gamma, opts)
     arena = to_dev(U0)
     mesh = H.Mesh(m, arena)
     pks = [H.Packet(mesh, range(9 * k, 9 * k + 9), H.FP64 | EF) for k in range(3)]
@@ -115,12 +122,39 @@ def test_uniform_state_bitwise(variant, prec):
 def test_host_resident_packets(variant):
     import torch
 
-    EF, sp = variant
+    EF, opts = variant
     P = I.uneven(nblocks=40, nsteps=6)
-    R, _, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, sp)
+    R, _, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, opts)
     host = torch.from_numpy(P.U0.copy()).pin_memory()
     hs = H.HostStream(P.mesh, host, P.packets, H.FP64 | EF, 2)
     t = hs.run(P.nsteps, P.cfl, P.gamma)
     hs.close()
     assert abs(t - t_ref) <= 1e-12 * t_ref
     assert rel_err(P.mesh, host.numpy(), R) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
+def test_conserved_reconstruction_reports_non_physical_face_state(prec):
+    """Velocity shear at low pressure: every cell is physical, but conserved
+    reconstruction gives face states with p < 0 (the oracle reports them);
+    the step must fail with HYDRO_ENONPHYS, and primitive reconstruction of
+    the same state must not."""
+    m = I.block_grid((1, 1, 1), (16, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    prims = I.grid_field(m, lambda x, y, z: (1.0, 5 * np.sin(2 * np.pi * x), 0.0, 0.0, 0.1))
+    U0 = I.conserved_arena(m, prims, 1.4)
+    O.run(m, U0.copy(), 1, 0.4, 1.4)  # primitive reconstruction: a physical step
+    with pytest.raises(O.OracleError) as e:
+        O.run(m, U0.copy(), 1, 0.4, 1.4, recon=O.CONSERVED)
+    assert e.value.code == O.ENONPHYS
+    for flags, ok in ((0, True), (H.CONSERVED, False)):
+        arena = to_dev(U0)
+        mesh = H.Mesh(m, arena)
+        b = H.Batch([H.Packet(mesh, range(m.nblocks), prec | flags)])
+        if ok:
+            b.run(1, 0.4, 1.4)
+        else:
+            with pytest.raises(H.HydroError) as e:
+                b.run(1, 0.4, 1.4)
+            assert e.value.code == H.ENONPHYS
+        b.close()
+        mesh.close()
