@@ -22,9 +22,10 @@
  * The paper does not spell out the reconstruction, the Riemann solver or the
  * time-step rule.  This reference fixes them to named textbook methods:
  *   - PLM (van Leer 1979) on primitive variables (rho, u, v, w, p) with the
- *     minmod limiter (Roe 1986), one direction at a time, unsplit; as a
- *     method variant, PLM on the conserved variables with the face states
- *     recovered afterwards;
+ *     minmod limiter (Roe 1986), one direction at a time, unsplit; as
+ *     method variants, PLM on the conserved variables with the face states
+ *     recovered afterwards, or on the characteristic variables of the
+ *     primitive system (Toro 2009, ch. 3 and sec. 14.4);
  *   - HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; Toro,
  *     "Riemann Solvers and Numerical Methods for Fluid Dynamics", 3rd ed.,
  *     ch. 10) with Davis (1988) wave-speed bounds, or, as method variants,
@@ -42,8 +43,8 @@
  * interior layers), periodic on the block itself (wrap), or outflow
  * (zero-gradient copy of the first interior layer into both guard layers).
  * No floors: a non-positive density or pressure, or a non-finite value, in a
- * recovered state (a cell's, or with conserved reconstruction a face
- * state's) is an error (ORACLE_ENONPHYS).
+ * recovered state (a cell's, or with conserved or characteristic
+ * reconstruction a face state's) is an error (ORACLE_ENONPHYS).
  *
  * Build: -O2 -ffp-contract=off -fno-fast-math, so every operation is rounded
  * as written.  OpenMP runs blocks of one stage in parallel; every block's
@@ -69,7 +70,7 @@
 enum { ORACLE_NBR = 0, ORACLE_OUTFLOW = 1, ORACLE_PERIODIC_SELF = 2 };
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 3, ORACLE_ENONPHYS = 4 };
 enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1, ORACLE_SPEEDS_PVRS = 2 };
-enum { ORACLE_RECON_PRIMITIVE = 0, ORACLE_RECON_CONSERVED = 1 };
+enum { ORACLE_RECON_PRIMITIVE = 0, ORACLE_RECON_CONSERVED = 1, ORACLE_RECON_CHARACTERISTIC = 2 };
 
 typedef struct {
   int32_t nblocks;
@@ -80,7 +81,7 @@ typedef struct {
   const int32_t *nbr;    /* [nblocks][6] neighbour block id of ORACLE_NBR faces */
   const int64_t *offset; /* [nblocks] element offset of variable 0 in the arena */
   int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS, _EINFELDT or _PVRS */
-  int32_t recon;         /* PLM variables: ORACLE_RECON_PRIMITIVE or _CONSERVED */
+  int32_t recon;         /* PLM variables: ORACLE_RECON_PRIMITIVE, _CONSERVED or _CHARACTERISTIC */
 } oracle_mesh;
 
 /* ------------------------------------------------------------------------ */
@@ -198,17 +199,49 @@ void oracle_plm_face(const double *w, double *wl, double *wr) {
   }
 }
 
+/* Limited slope of cell W (primitives) on the characteristic variables of
+ * the primitive Euler system along direction `dir` (Toro 2009, ch. 3: the
+ * system W_t + A W_x = 0 with normal velocity u_n = W[1 + dir], waves
+ * u_n - c, u_n (entropy and two shear waves), u_n + c), from the one-sided
+ * differences da = W - W_left and db = W_right - W:
+ *   amplitudes of a difference d (left eigenvectors at W, rho c = impedance):
+ *     a_-  = (d_p - rho c d_un) / (2 c^2),   a_0 = d_rho - d_p / c^2,
+ *     a_t1 = d_ut1,  a_t2 = d_ut2,           a_+ = (d_p + rho c d_un) / (2 c^2);
+ *   each amplitude limited by minmod of its two one-sided values, m_k;
+ *   slope = sum_k m_k r_k with the right eigenvectors at W:
+ *     d_rho = m_- + m_0 + m_+,  d_un = (c / rho)(m_+ - m_-),
+ *     d_ut = m_t,               d_p  = c^2 (m_- + m_+). */
+static void char_slope(const double *W, const double *da, const double *db, double gamma, int dir, double *s) {
+  int n = 1 + dir, t1 = 1 + (dir + 1) % 3, t2 = 1 + (dir + 2) % 3;
+  double c = sqrt(gamma * W[4] / W[0]);
+  double rc = W[0] * c, c2 = c * c;
+  double am = oracle_minmod((da[4] - rc * da[n]) / (2.0 * c2), (db[4] - rc * db[n]) / (2.0 * c2));
+  double a0 = oracle_minmod(da[0] - da[4] / c2, db[0] - db[4] / c2);
+  double at1 = oracle_minmod(da[t1], db[t1]);
+  double at2 = oracle_minmod(da[t2], db[t2]);
+  double ap = oracle_minmod((da[4] + rc * da[n]) / (2.0 * c2), (db[4] + rc * db[n]) / (2.0 * c2));
+  s[0] = am + a0 + ap;
+  s[n] = (c / W[0]) * (ap - am);
+  s[t1] = at1;
+  s[t2] = at2;
+  s[4] = c2 * (am + ap);
+}
+
 /* Primitive face states at the face between cells 1 and 2 of four
- * consecutive cells given by their conserved values u[0..3] ([4][NVAR]).
- * Every cell's primitives are recovered first (a non-physical cell is an
- * error).  Then PLM runs on the variables `recon` names:
+ * consecutive cells along direction dir (0 x, 1 y, 2 z) given by their
+ * conserved values u[0..3] ([4][NVAR]).  Every cell's primitives are
+ * recovered first (a non-physical cell is an error).  Then PLM runs on the
+ * variables `recon` names:
  *   ORACLE_RECON_PRIMITIVE: on the recovered (rho, u, v, w, p);
  *   ORACLE_RECON_CONSERVED: on (rho, rho u, rho v, rho w, E) themselves
  *     (van Leer's MUSCL on the conserved variables), after which the two face
- *     states are recovered with the same formulas; a non-physical face state
- *     (rho <= 0, p <= 0, non-finite) is an error as well.
- * Returns ORACLE_OK or ORACLE_ENONPHYS. */
-int oracle_face_states(const double *u, double gamma, int recon, double *wl, double *wr) {
+ *     states are recovered with the same formulas;
+ *   ORACLE_RECON_CHARACTERISTIC: on the characteristic variables of each of
+ *     the two cells (char_slope): left state W_1 + slope_1 / 2, right state
+ *     W_2 - slope_2 / 2.
+ * With the last two a non-physical face state (rho <= 0, p <= 0,
+ * non-finite) is an error as well.  Returns ORACLE_OK or ORACLE_ENONPHYS. */
+int oracle_face_states(const double *u, double gamma, int recon, int dir, double *wl, double *wr) {
   double w[4][NVAR];
   for (int s = 0; s < 4; ++s) {
     oracle_prim(u + s * NVAR, gamma, w[s]);
@@ -219,10 +252,24 @@ int oracle_face_states(const double *u, double gamma, int recon, double *wl, dou
     oracle_plm_face(u, ul, ur);
     oracle_prim(ul, gamma, wl);
     oracle_prim(ur, gamma, wr);
-    if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;
+  } else if (recon == ORACLE_RECON_CHARACTERISTIC) {
+    double d01[NVAR], d12[NVAR], d23[NVAR], s1[NVAR], s2[NVAR];
+    for (int v = 0; v < NVAR; ++v) {
+      d01[v] = w[1][v] - w[0][v];
+      d12[v] = w[2][v] - w[1][v];
+      d23[v] = w[3][v] - w[2][v];
+    }
+    char_slope(w[1], d01, d12, gamma, dir, s1);
+    char_slope(w[2], d12, d23, gamma, dir, s2);
+    for (int v = 0; v < NVAR; ++v) {
+      wl[v] = w[1][v] + 0.5 * s1[v];
+      wr[v] = w[2][v] - 0.5 * s2[v];
+    }
   } else {
     oracle_plm_face(&w[0][0], wl, wr);
+    return ORACLE_OK;
   }
+  if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;
   return ORACLE_OK;
 }
 
@@ -379,7 +426,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
             for (int v = 0; v < NVAR; ++v) u[s][v] = S.q[pidx(&S, v, c[0], c[1], c[2])];
           }
           double wl[NVAR], wr[NVAR], rl[NVAR], rr[NVAR], f[NVAR];
-          rc = oracle_face_states(&u[0][0], gamma, m->recon, wl, wr);
+          rc = oracle_face_states(&u[0][0], gamma, m->recon, d, wl, wr);
           if (rc) break;
           /* rotate: the normal velocity component goes into slot 1 */
           for (int v = 0; v < NVAR; ++v) {
@@ -442,7 +489,7 @@ int oracle_validate(const oracle_mesh *m) {
   if (!m || m->nblocks < 0 || (m->ndim != 2 && m->ndim != 3)) return ORACLE_EINVAL;
   if (m->nblocks > 0 && (!m->n || !m->dx || !m->kind || !m->nbr || !m->offset)) return ORACLE_EINVAL;
   if (m->speeds < ORACLE_SPEEDS_DAVIS || m->speeds > ORACLE_SPEEDS_PVRS) return ORACLE_EINVAL;
-  if (m->recon != ORACLE_RECON_PRIMITIVE && m->recon != ORACLE_RECON_CONSERVED) return ORACLE_EINVAL;
+  if (m->recon < ORACLE_RECON_PRIMITIVE || m->recon > ORACLE_RECON_CHARACTERISTIC) return ORACLE_EINVAL;
   for (int b = 0; b < m->nblocks; ++b) {
     const int32_t *n = m->n + 3 * b;
     if (m->ndim == 2 && n[2] != 1) return ORACLE_EINVAL;

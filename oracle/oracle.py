@@ -23,7 +23,7 @@ _OVERRIDE = os.environ.get("HYDRO_ORACLE_LIB")
 
 OK, EINVAL, ENOMEM, ENONPHYS = 0, 1, 3, 4
 DAVIS, EINFELDT, PVRS = 0, 1, 2  # HLLC wave-speed bounds
-PRIMITIVE, CONSERVED = 0, 1  # variables PLM reconstructs
+PRIMITIVE, CONSERVED, CHARACTERISTIC = 0, 1, 2  # variables PLM reconstructs
 
 
 class OracleError(RuntimeError):
@@ -62,7 +62,7 @@ def lib():
         L.oracle_minmod.argtypes = [C.c_double, C.c_double]
         L.oracle_minmod.restype = C.c_double
         L.oracle_plm_face.argtypes = [dp, dp, dp]
-        L.oracle_face_states.argtypes = [dp, C.c_double, C.c_int, dp, dp]
+        L.oracle_face_states.argtypes = [dp, C.c_double, C.c_int, C.c_int, dp, dp]
         L.oracle_hllc.argtypes = [dp, dp, C.c_double, dp]
         L.oracle_hllc_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
         L.oracle_wave_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
@@ -131,13 +131,14 @@ def plm_face(w4) -> tuple[np.ndarray, np.ndarray]:
     return wl, wr
 
 
-def face_states(u4, gamma: float, recon: int = PRIMITIVE):
-    """Primitive face states between cells 1 and 2 of four cells given by
-    their conserved values ([4][5]); (wl, wr), or None if a cell or (with
-    conserved reconstruction) a face state is non-physical."""
+def face_states(u4, gamma: float, recon: int = PRIMITIVE, direction: int = 0):
+    """Primitive face states between cells 1 and 2 of four cells along
+    `direction` given by their conserved values ([4][5]); (wl, wr), or None
+    if a cell or (with conserved or characteristic reconstruction) a face
+    state is non-physical."""
     u = np.ascontiguousarray(u4, dtype=np.float64).reshape(4, 5)
     wl, wr = np.empty(5), np.empty(5)
-    rc = lib().oracle_face_states(_dptr(u), gamma, int(recon), _dptr(wl), _dptr(wr))
+    rc = lib().oracle_face_states(_dptr(u), gamma, int(recon), int(direction), _dptr(wl), _dptr(wr))
     return None if rc == ENONPHYS else (wl, wr)
 
 

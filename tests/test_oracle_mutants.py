@@ -48,8 +48,14 @@ MUTANTS = {
     "recon-conserved-uses-primitives": ("    oracle_plm_face(u, ul, ur);", "    oracle_plm_face(&w[0][0], ul, ur);"),
     "recon-no-face-state-check": ("if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;", "(void)0;"),
     "recon-right-state-from-left": ("    oracle_prim(ur, gamma, wr);", "    oracle_prim(ul, gamma, wr);"),
-    "recon-option-ignored": ("oracle_face_states(&u[0][0], gamma, m->recon, wl, wr);",
-                             "oracle_face_states(&u[0][0], gamma, ORACLE_RECON_PRIMITIVE, wl, wr);"),
+    "recon-option-ignored": ("oracle_face_states(&u[0][0], gamma, m->recon, d, wl, wr);",
+                             "oracle_face_states(&u[0][0], gamma, ORACLE_RECON_PRIMITIVE, d, wl, wr);"),
+    "char-impedance-sign": ("double ap = oracle_minmod((da[4] + rc * da[n])", "double ap = oracle_minmod((da[4] - rc * da[n])"),
+    "char-entropy-drops-pressure": ("double a0 = oracle_minmod(da[0] - da[4] / c2, db[0] - db[4] / c2);",
+                                    "double a0 = oracle_minmod(da[0], db[0] - db[4] / c2);"),
+    "char-velocity-back-factor": ("s[n] = (c / W[0]) * (ap - am);", "s[n] = (c * W[0]) * (ap - am);"),
+    "char-normal-index": ("int n = 1 + dir,", "int n = 1,"),
+    "char-right-slope-cell": ("char_slope(w[2], d12, d23, gamma, dir, s2);", "char_slope(w[1], d12, d23, gamma, dir, s2);"),
 }
 
 

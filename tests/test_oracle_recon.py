@@ -1,4 +1,5 @@
-"""Pins of the conserved-variable reconstruction variant of the oracle.
+"""Pins of the reconstruction variants of the oracle: PLM on the conserved
+variables, and PLM on the characteristic variables.
 
 With this option PLM (minmod) runs on (rho, rho u, rho v, rho w, E) and the
 two face states are recovered to primitives afterwards (van Leer's MUSCL on
@@ -19,6 +20,17 @@ non-physical cell is.  Pinned without re-typing the formulas:
     than first order;
   * the scheme keeps uniform states bitwise, conserves, keeps blast mirror
     symmetry and converges on Sod; the option reaches the step.
+
+Characteristic reconstruction limits, per cell, the amplitudes of the
+one-sided differences on the waves of the primitive system along the face
+normal (u - c, entropy, two shear waves, u + c) and maps the limited
+amplitudes back.  Pinned through an eigen-decomposition of the primitive
+Jacobian built here and solved with numpy (acoustic eigenvectors from
+numpy.linalg.eig, the three-fold eigenvalue u spanned by the density-only
+and tangential-velocity vectors; minmod is odd-homogeneous, so the scaling
+of the eigenvectors does not matter), in every direction; linear data and a
+contact at rest reduce to primitive reconstruction; an acoustic extremum
+keeps a slope that primitive reconstruction clips.
 """
 import math
 
@@ -142,5 +154,131 @@ def test_scheme_with_conserved_reconstruction_invariants():
 
 def test_unknown_reconstruction_rejected():
     mesh = I.block_grid((1, 1, 1), (8, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
-    assert O.validate(mesh, O.DAVIS, 2) == O.EINVAL and O.validate(mesh, O.DAVIS, -1) == O.EINVAL
-    assert O.validate(mesh, O.PVRS, CONS) == O.OK
+    assert O.validate(mesh, O.DAVIS, 3) == O.EINVAL and O.validate(mesh, O.DAVIS, -1) == O.EINVAL
+    assert O.validate(mesh, O.PVRS, CONS) == O.OK and O.validate(mesh, O.EINFELDT, O.CHARACTERISTIC) == O.OK
+
+
+# ------------------------------------------------------ characteristic PLM
+CHAR = O.CHARACTERISTIC
+
+
+def cons_of(W, g):
+    r, vel, p = W[0], np.asarray(W[1:4]), W[4]
+    return np.array([r, *(r * vel), p / (g - 1.0) + 0.5 * r * float(vel @ vel)])
+
+
+def minmod(a, b):
+    return np.where((a > 0) & (b > 0), np.minimum(a, b), np.where((a < 0) & (b < 0), np.maximum(a, b), 0.0))
+
+
+def eig_slope(W, da, db, g, direction):
+    """Limited characteristic slope of cell W from an eigen-decomposition of
+    the primitive Jacobian along `direction`, computed with numpy."""
+    n = 1 + direction
+    r, un, p = W[0], W[n], W[4]
+    c2 = g * p / r
+    # (rho, u_n, p) block of the Jacobian; the tangential velocities are
+    # advected (eigenvalue u_n)
+    A = np.array([[un, r, 0.0], [0.0, un, 1.0 / r], [0.0, r * c2, un]])
+    lam, V = np.linalg.eig(A)
+    order = np.argsort(lam.real)
+    V = V[:, order].real  # columns: u - c, u (entropy), u + c
+    R = np.zeros((5, 5))
+    idx = [0, n, 4]
+    tang = [k for k in (1, 2, 3) if k != n]
+    R[idx, 0] = V[:, 0]               # acoustic waves from numpy
+    R[idx, 4] = V[:, 2]
+    R[0, 1] = 1.0                     # entropy wave: density only
+    R[tang[0], 2] = 1.0               # shear waves
+    R[tang[1], 3] = 1.0
+    a = np.linalg.solve(R, da)
+    b = np.linalg.solve(R, db)
+    return R @ minmod(a, b)
+
+
+def random_prims(rng):
+    return np.array([rng.uniform(0.5, 2.0), *rng.normal(0, 1, 3), rng.uniform(0.5, 2.0)])
+
+
+def test_characteristic_slopes_match_eigen_decomposition():
+    rng = np.random.default_rng(41)
+    g = 1.4
+    checked = 0
+    for _ in range(300):
+        direction = int(rng.integers(0, 3))
+        base = random_prims(rng)
+        W = [base + 0.15 * rng.normal(0, 1, 5) for _ in range(4)]
+        if min(w[0] for w in W) <= 0.1 or min(w[4] for w in W) <= 0.1:
+            continue
+        u4 = np.array([cons_of(w, g) for w in W])
+        res = O.face_states(u4, g, CHAR, direction)
+        Wr = [O.prim(u, g) for u in u4]  # the oracle's own recovered cells
+        s1 = eig_slope(Wr[1], Wr[1] - Wr[0], Wr[2] - Wr[1], g, direction)
+        s2 = eig_slope(Wr[2], Wr[2] - Wr[1], Wr[3] - Wr[2], g, direction)
+        el, er = Wr[1] + 0.5 * s1, Wr[2] - 0.5 * s2
+        if min(el[0], el[4], er[0], er[4]) <= 0:
+            assert res is None
+            continue
+        wl, wr = res
+        scale = np.abs(np.concatenate([w for w in Wr])).max()
+        assert np.abs(wl - el).max() <= 1e-13 * scale and np.abs(wr - er).max() <= 1e-13 * scale
+        checked += 1
+    assert checked >= 150
+
+
+def test_characteristic_equals_primitive_on_linear_data_and_contacts():
+    rng = np.random.default_rng(42)
+    g = 1.4
+    for _ in range(100):
+        base = random_prims(rng)
+        d = 0.05 * rng.normal(0, 1, 5)
+        u4 = np.array([cons_of(base + s * d, g) for s in range(4)])
+        direction = int(rng.integers(0, 3))
+        cl, cr = O.face_states(u4, g, CHAR, direction)
+        pl, pr = O.face_states(u4, g, O.PRIMITIVE, direction)
+        # the recovered cells are linear only to rounding: compare to it
+        scale = np.abs(base).max()
+        assert np.abs(cl - pl).max() <= 1e-12 * scale and np.abs(cr - pr).max() <= 1e-12 * scale
+    # contact at rest: density jumps, u and p uniform -> only the entropy wave
+    W = [np.array([r, 0.3, -0.2, 0.1, 1.0]) for r in (1.0, 1.0, 0.125, 0.125)]
+    u4 = np.array([cons_of(w, g) for w in W])
+    for direction in range(3):
+        cl, cr = O.face_states(u4, g, CHAR, direction)
+        pl, pr = O.face_states(u4, g, O.PRIMITIVE, direction)
+        assert np.abs(cl - pl).max() <= 1e-15 and np.abs(cr - pr).max() <= 1e-15
+
+
+def test_characteristic_keeps_acoustic_slope_at_pressure_extremum():
+    """A right-going acoustic wave plus a left-going one of opposite
+    curvature: the pressure has an extremum at cell 1, so primitive PLM clips
+    the pressure slope to 0, while both acoustic amplitudes keep a slope of
+    one sign; here rho = 1, c = 1 and the limited slopes are computed by hand:
+    d_lo = (du, dp) = (0.1, 0.05), d_hi = (0.1, -0.05) give amplitudes
+    a_+ = (0.075, 0.025), a_- = (-0.025, -0.075), limited 0.025 and -0.025,
+    so du = (c/rho)(0.025 + 0.025) = 0.05 and dp = 0."""
+    g = 1.4
+    p1 = 1.0 / g  # c = sqrt(g p / rho) = 1
+    W1 = np.array([1.0, 0.0, 0.0, 0.0, p1])
+    W0 = W1 - np.array([0.05, 0.1, 0, 0, 0.05])  # d_rho = d_p / c^2: no entropy wave
+    W2 = W1 + np.array([-0.05, 0.1, 0, 0, -0.05])
+    W3 = W2 + (W2 - W1)
+    u4 = np.array([cons_of(w, g) for w in (W0, W1, W2, W3)])
+    Wr = [O.prim(u, g) for u in u4]
+    wl, _ = O.face_states(u4, g, CHAR, 0)
+    pl, _ = O.face_states(u4, g, O.PRIMITIVE, 0)
+    assert abs(pl[1] - (Wr[1][1] + 0.05)) <= 1e-12 and abs(pl[4] - Wr[1][4]) <= 1e-12
+    assert abs(wl[1] - (Wr[1][1] + 0.025)) <= 1e-12 and abs(wl[4] - Wr[1][4]) <= 1e-12
+
+
+def test_scheme_with_characteristic_reconstruction():
+    # Sod: converges, and the option reaches the step
+    errs = [sod_l1(n, O.DAVIS, CHAR)[0] for n in (64, 128, 256)]
+    assert errs[0] <= 2e-2
+    assert errs[0] / errs[1] >= 1.5 and errs[1] / errs[2] >= 1.5, errs
+    assert not np.array_equal(sod_l1(64, O.DAVIS, CHAR)[1], sod_l1(64, O.DAVIS)[1])
+    # advection at uniform u, p: only the entropy wave, so primitive PLM to rounding
+    a = advect(64, O.PRIMITIVE)[1]
+    b = advect(64, CHAR)[1]
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    check_scheme_invariants(O.DAVIS, CHAR)
+
