@@ -316,12 +316,14 @@ def main():
                                             for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
 
-    # method variants (Einfeldt, PVRS wave speeds; conserved reconstruction):
+    # method variants (Einfeldt, PVRS wave speeds; conserved, characteristic PLM):
     # kernel time of a few eager steps
     variants = {}
     for name, prec in (("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT), ("fp64_einfeldt", H.FP64 | H.EINFELDT),
                        ("mixed_pvrs", H.FP32_FP64 | H.PVRS), ("fp64_pvrs", H.FP64 | H.PVRS),
-                       ("mixed_conserved", H.FP32_FP64 | H.CONSERVED), ("fp64_conserved", H.FP64 | H.CONSERVED)):
+                       ("mixed_conserved", H.FP32_FP64 | H.CONSERVED), ("fp64_conserved", H.FP64 | H.CONSERVED),
+                       ("mixed_characteristic", H.FP32_FP64 | H.CHARACTERISTIC),
+                       ("fp64_characteristic", H.FP64 | H.CHARACTERISTIC)):
         arena.copy_(U0_dev)
         b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
         k = b.time_kernels(min(args.steps, 5), P.cfl, P.gamma)

@@ -21,8 +21,8 @@
  * Reconstruction, Riemann solver and time-step rule are not given by the paper
  * and follow the textbook methods: PLM (van Leer 1979) on primitive variables
  * with minmod (Roe 1986); HLLC (Toro, Spruce & Speares 1994) with Davis
- * wave speeds (Einfeldt or PVRS as variants; PLM on conserved variables as a
- * further variant); SSP-RK2 (Shu & Osher 1988);
+ * wave speeds (Einfeldt or PVRS as variants; PLM on conserved or on
+ * characteristic variables as further variants); SSP-RK2 (Shu & Osher 1988);
  * dt = CFL / max_c sum_d (|u_d|+c)/dx_d.
  *
  * Conventions for every call
@@ -94,6 +94,15 @@ typedef enum {
  * produces one, where primitive reconstruction keeps p > 0. */
 #define HYDRO_RECON_CONSERVED 0x400
 
+/* Reconstruction variant (not together with HYDRO_RECON_CONSERVED): PLM on
+ * the characteristic variables of the primitive Euler system along each
+ * face normal (Toro 2009, ch. 3): the one-sided differences of a cell are
+ * split into the amplitudes of its waves u - c, entropy, two shear waves and
+ * u + c, each amplitude is limited with minmod, and the slope is rebuilt from
+ * the cell's right eigenvectors.  Non-physical face states are
+ * HYDRO_ENONPHYS as above. */
+#define HYDRO_RECON_CHARACTERISTIC 0x800
+
 typedef enum {
   HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
   HYDRO_OUTFLOW = 1,      /* zero gradient: both guard layers copy the edge layer        */
@@ -137,7 +146,7 @@ hydro_status hydro_mesh_destroy(hydro_mesh *m);
 
 /* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
  * listed blocks of mesh m, advanced in the given hydro_precision (optionally
- * OR at most one HYDRO_SPEEDS_* variant and HYDRO_RECON_CONSERVED).  block_ids:
+ * OR at most one HYDRO_SPEEDS_* and one HYDRO_RECON_* variant).  block_ids:
  * host array of nblocks distinct ids.  Builds the packet's device work list.
  * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
  * EDEVICE. */

@@ -391,17 +391,19 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
 // A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
-// with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS and with
-// HYDRO_RECON_CONSERVED.
+// with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS and one of
+// HYDRO_RECON_CONSERVED, HYDRO_RECON_CHARACTERISTIC.
 bool prec_valid(int32_t p) {
   const int32_t base = p & 0xff, sp = p & (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS);
-  const int32_t rest = p & ~(0xff | HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS | HYDRO_RECON_CONSERVED);
+  const int32_t rc = p & (HYDRO_RECON_CONSERVED | HYDRO_RECON_CHARACTERISTIC);
+  const int32_t rest = p & ~(0xff | HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS | HYDRO_RECON_CONSERVED |
+                             HYDRO_RECON_CHARACTERISTIC);
   return rest == 0 && sp != (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS) &&
-         (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
+         rc != (HYDRO_RECON_CONSERVED | HYDRO_RECON_CHARACTERISTIC) && (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
 }
 bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
 int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : (p & HYDRO_SPEEDS_PVRS) ? 2 : 0; }
-int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : 0; }
+int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : (p & HYDRO_RECON_CHARACTERISTIC) ? 2 : 0; }
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a) {

@@ -68,7 +68,7 @@ struct StageArgs {
 
 // kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
 // speeds: 0 = Davis, 1 = Einfeldt, 2 = pressure-based (PVRS) wave-speed bounds in HLLC.
-// recon: 0 = PLM on primitives, 1 = PLM on conserved variables.
+// recon: 0 = PLM on primitives, 1 = on conserved variables, 2 = on characteristic variables.
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,
                         const StageArgs &a);
 hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a);

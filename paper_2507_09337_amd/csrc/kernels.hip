@@ -4,10 +4,11 @@
 // Method (arXiv 2507.09337, Sec. 6: explicit finite volume with a guard-cell
 // halo, 2nd-order Runge-Kutta refreshing guards before each stage; Sec. 5.2:
 // ideal-gas gamma-law EOS).  Reconstruction and flux follow the textbook
-// methods named in include/hydro.h: PLM on primitives with minmod (or, as a
-// variant, on the conserved variables with the face states recovered
-// afterwards), HLLC with Davis (or, as variants, Einfeldt or PVRS) wave
-// speeds, SSP-RK2 combine, CFL rate sum_d (|u_d| + c)/dx_d.
+// methods named in include/hydro.h: PLM on primitives with minmod (or, as
+// variants, on the conserved variables with the face states recovered
+// afterwards, or on the characteristic variables of the primitive system),
+// HLLC with Davis (or, as variants, Einfeldt or PVRS) wave speeds, SSP-RK2
+// combine, CFL rate sum_d (|u_d| + c)/dx_d.
 //
 // Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
 //   * One workgroup = 256 threads = one x-y tile of a block (16x16) or four
@@ -78,7 +79,7 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
 
 enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1, SPEEDS_PVRS = 2 };
 // Variables PLM reconstructs.
-enum { RECON_PRIMITIVE = 0, RECON_CONSERVED = 1 };
+enum { RECON_PRIMITIVE = 0, RECON_CONSERVED = 1, RECON_CHARACTERISTIC = 2 };
 
 // HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).  Wave
 // speed bounds: Davis, min/max of u -+ c over both sides; or Einfeldt,
@@ -206,6 +207,59 @@ __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], 
   const double Us[5] = {a, a * Ss, a * v, a * w, a * (E / r + (Ss - u) * (Ss + p / (r * (SK - u))))};
 #pragma unroll
   for (int k = 0; k < 5; ++k) F[k] = star ? FK[k] + SK * (Us[k] - UK[k]) : FK[k];
+}
+
+// Characteristic limiting in FP64 (Toro 2009, ch. 3), in the face frame
+// (normal velocity in slot 1): the one-sided differences da, db of cell W
+// are split into the amplitudes of the waves u - c, entropy, two shear
+// waves, u + c (left eigenvectors at W, impedance rho c):
+//   a_- = (d_p - rho c d_u)/(2 c^2), a_0 = d_rho - d_p/c^2, a_t = d_t,
+//   a_+ = (d_p + rho c d_u)/(2 c^2);
+// each is limited by minmod and the slope rebuilt from the right
+// eigenvectors: d_rho = m_- + m_0 + m_+, d_u = (c/rho)(m_+ - m_-),
+// d_t = m_t, d_p = c^2 (m_- + m_+).  Operation order of the plain
+// statement, no contraction (IEEE division and square root).
+__device__ __forceinline__ void char_slope_fp64(const double W[5], const double da[5], const double db[5], double g,
+                                                double s[5]) {
+#pragma clang fp contract(off)
+  const double c = __builtin_sqrt(g * W[4] / W[0]);
+  const double rc = W[0] * c, c2 = c * c;
+  const double am = minmod((da[4] - rc * da[1]) / (2.0 * c2), (db[4] - rc * db[1]) / (2.0 * c2));
+  const double a0 = minmod(da[0] - da[4] / c2, db[0] - db[4] / c2);
+  const double at1 = minmod(da[2], db[2]);
+  const double at2 = minmod(da[3], db[3]);
+  const double ap = minmod((da[4] + rc * da[1]) / (2.0 * c2), (db[4] + rc * db[1]) / (2.0 * c2));
+  s[0] = am + a0 + ap;
+  s[1] = (c / W[0]) * (ap - am);
+  s[2] = at1;
+  s[3] = at2;
+  s[4] = c2 * (am + ap);
+}
+
+// Face states between cells 1 and 2 of four cells w (face frame) with
+// characteristic limiting: left W_1 + slope_1/2, right W_2 - slope_2/2.
+__device__ __forceinline__ void char_states_fp64(const double (&w)[4][5], double g, double L[5], double R[5]) {
+#pragma clang fp contract(off)
+  double d01[5], d12[5], d23[5], s1[5], s2[5];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) {
+    d01[v] = w[1][v] - w[0][v];
+    d12[v] = w[2][v] - w[1][v];
+    d23[v] = w[3][v] - w[2][v];
+  }
+  char_slope_fp64(w[1], d01, d12, g, s1);
+  char_slope_fp64(w[2], d12, d23, g, s2);
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) {
+    L[v] = w[1][v] + 0.5 * s1[v];
+    R[v] = w[2][v] - 0.5 * s2[v];
+  }
+}
+
+// A reconstructed face state is physical: rho > 0, p > 0, all finite.
+__device__ __forceinline__ bool state_ok(const double s[5]) {
+  const double m = fabs(s[1]) + fabs(s[2]) + fabs(s[3]) + s[4] + s[0];
+  return (s[0] > 0.0) && (s[4] > 0.0) && (m < __builtin_huge_val());
 }
 
 // FP64 primitive recovery (ideal gas), in the plain evaluation order
@@ -512,16 +566,42 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
         out = Fy + row * TX + col;
         ostride = NYF;
       }
-      T wl[5], wr[5];
+      T Lr[5], Rr[5];
+      if constexpr (RECON == RECON_CHARACTERISTIC) {
+        T w[4][5];  // the four cells in the face frame
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        const T *p = Wp + v * PP + base;
-        plm(p[0], p[stride], p[2 * stride], p[3 * stride], wl[v], wr[v]);
+        for (int k = 0; k < 4; ++k) {
+          const T *p = Wp + base + k * stride;
+          w[k][0] = p[0];
+          w[k][1] = isx ? p[PP] : p[2 * PP];
+          w[k][2] = isx ? p[2 * PP] : p[PP];
+          w[k][3] = p[3 * PP];
+          w[k][4] = p[4 * PP];
+        }
+        char_states_fp64(w, gamma, Lr, Rr);
+        if (!(state_ok(Lr) && state_ok(Rr)) && active) {
+          bad = 1;
+          badblk = min(badblk, b);
+        }
+      } else {
+        T wl[5], wr[5];
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          const T *p = Wp + v * PP + base;
+          plm(p[0], p[stride], p[2 * stride], p[3 * stride], wl[v], wr[v]);
+        }
+        face_prims(wl);
+        face_prims(wr);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          Lr[v] = wl[v];
+          Rr[v] = wr[v];
+        }
+        Lr[1] = isx ? wl[1] : wl[2];
+        Lr[2] = isx ? wl[2] : wl[1];
+        Rr[1] = isx ? wr[1] : wr[2];
+        Rr[2] = isx ? wr[2] : wr[1];
       }
-      face_prims(wl);
-      face_prims(wr);
-      const T Lr[5] = {wl[0], isx ? wl[1] : wl[2], isx ? wl[2] : wl[1], wl[3], wl[4]};
-      const T Rr[5] = {wr[0], isx ? wr[1] : wr[2], isx ? wr[2] : wr[1], wr[3], wr[4]};
       T Fr[5];
       hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
       out[0] = Fr[0];
@@ -621,13 +701,31 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     if (active) prims(Ud, Wd, true);
     T fz[5];
     {
-      T wl[5], wr[5];
+      T Lr[5], Rr[5];
+      if constexpr (RECON == RECON_CHARACTERISTIC) {
+        const T w[4][5] = {{Wa[0], Wa[3], Wa[2], Wa[1], Wa[4]},
+                           {Wb[0], Wb[3], Wb[2], Wb[1], Wb[4]},
+                           {Wc[0], Wc[3], Wc[2], Wc[1], Wc[4]},
+                           {Wd[0], Wd[3], Wd[2], Wd[1], Wd[4]}};
+        char_states_fp64(w, gamma, Lr, Rr);
+        if (!(state_ok(Lr) && state_ok(Rr)) && active) {
+          bad = 1;
+          badblk = min(badblk, b);
+        }
+      } else {
+        T wl[5], wr[5];
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) plm(Wa[v], Wb[v], Wc[v], Wd[v], wl[v], wr[v]);
-      face_prims(wl);
-      face_prims(wr);
-      const T Lr[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
-      const T Rr[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
+        for (int v = 0; v < NVAR; ++v) plm(Wa[v], Wb[v], Wc[v], Wd[v], wl[v], wr[v]);
+        face_prims(wl);
+        face_prims(wr);
+        const T l[5] = {wl[0], wl[3], wl[2], wl[1], wl[4]};
+        const T r[5] = {wr[0], wr[3], wr[2], wr[1], wr[4]};
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          Lr[v] = l[v];
+          Rr[v] = r[v];
+        }
+      }
       T Fr[5];
       hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
       fz[0] = Fr[0];
@@ -668,6 +766,26 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
 // minmod in FP32 as the median of (a, b, 0): one v_med3_f32.
 __device__ __forceinline__ float minmod_f(float a, float b) {
   return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+
+// Characteristic limiting in FP32 (the FP64 statement above, with hardware
+// reciprocals): slope s of cell W (primitives, x, y, z frame) from its
+// one-sided differences da, db, along the axis whose velocity is slot N.
+template <int N>
+__device__ __forceinline__ void char_slope_f32(const float W[5], const float da[5], const float db[5], float g,
+                                               float s[5]) {
+#pragma clang fp contract(off)
+  const float c = Arith<float>::sound(g, W[4], W[0]);
+  const float rc = W[0] * c, c2 = c * c;
+  const float ic2 = __builtin_amdgcn_rcpf(c2), h = 0.5f * ic2;  // 1/c^2, 1/(2 c^2)
+  const float am = minmod_f(__builtin_fmaf(-rc, da[N], da[4]) * h, __builtin_fmaf(-rc, db[N], db[4]) * h);
+  const float ap = minmod_f(__builtin_fmaf(rc, da[N], da[4]) * h, __builtin_fmaf(rc, db[N], db[4]) * h);
+  const float a0 = minmod_f(__builtin_fmaf(-ic2, da[4], da[0]), __builtin_fmaf(-ic2, db[4], db[0]));
+  s[0] = am + a0 + ap;
+  s[4] = c2 * (am + ap);
+#pragma unroll
+  for (int k = 1; k <= 3; ++k)
+    s[k] = (k == N) ? (c * __builtin_amdgcn_rcpf(W[0])) * (ap - am) : minmod_f(da[k], db[k]);
 }
 
 // LDS layout of the mixed tile, per variable: the plane's primitives with
@@ -832,19 +950,60 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
   // swaps the two in-plane velocity components into the face frame and its
   // flux back.
   auto face = [&](int wb, int st, int o, bool isx) {
-    float a[5], r[5];
+    float Lr[5], Rr[5];
+    if constexpr (RECON == RECON_CHARACTERISTIC) {
+      // the four cells in the face frame (normal velocity in slot 1), then
+      // each state from its own cell's characteristic slope
+      float w[4][5];
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) {
-      const float *w = L + v * PP + wb;
-      const float w0 = w[0], w1 = w[st], w2 = w[2 * st], w3 = w[3 * st];
-      const float d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
-      a[v] = __builtin_fmaf(0.5f, minmod_f(d01, d12), w1);
-      r[v] = __builtin_fmaf(-0.5f, minmod_f(d12, d23), w2);
+      for (int k = 0; k < 4; ++k) {
+        const float *q = L + wb + k * st;
+        w[k][0] = q[0];
+        w[k][1] = isx ? q[PP] : q[2 * PP];
+        w[k][2] = isx ? q[2 * PP] : q[PP];
+        w[k][3] = q[3 * PP];
+        w[k][4] = q[4 * PP];
+      }
+      float d01[5], d12[5], d23[5], s1[5], s2[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        d01[v] = w[1][v] - w[0][v];
+        d12[v] = w[2][v] - w[1][v];
+        d23[v] = w[3][v] - w[2][v];
+      }
+      char_slope_f32<1>(w[1], d01, d12, g32, s1);
+      char_slope_f32<1>(w[2], d12, d23, g32, s2);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        Lr[v] = __builtin_fmaf(0.5f, s1[v], w[1][v]);
+        Rr[v] = __builtin_fmaf(-0.5f, s2[v], w[2][v]);
+      }
+      if (!(Lr[0] > 0.0f && Lr[4] > 0.0f && Rr[0] > 0.0f && Rr[4] > 0.0f) && active) {
+        bad = 1;
+        badblk = min(badblk, C.b);
+      }
+    } else {
+      float a[5], r[5];
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const float *w = L + v * PP + wb;
+        const float w0 = w[0], w1 = w[st], w2 = w[2 * st], w3 = w[3 * st];
+        const float d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
+        a[v] = __builtin_fmaf(0.5f, minmod_f(d01, d12), w1);
+        r[v] = __builtin_fmaf(-0.5f, minmod_f(d12, d23), w2);
+      }
+      face_prims(a);
+      face_prims(r);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        Lr[v] = a[v];
+        Rr[v] = r[v];
+      }
+      Lr[1] = isx ? a[1] : a[2];
+      Lr[2] = isx ? a[2] : a[1];
+      Rr[1] = isx ? r[1] : r[2];
+      Rr[2] = isx ? r[2] : r[1];
     }
-    face_prims(a);
-    face_prims(r);
-    const float Lr[5] = {a[0], isx ? a[1] : a[2], isx ? a[2] : a[1], a[3], a[4]};
-    const float Rr[5] = {r[0], isx ? r[1] : r[2], isx ? r[2] : r[1], r[3], r[4]};
     float F[5];
     hllc<SPEEDS>(Lr, Rr, g32, rgm1, F);
     float *q = L + o;
@@ -955,19 +1114,44 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     dlo[v] = Wc[v] - Wb[v];
     zp[v] = __builtin_fmaf(0.5f, minmod_f(Wb[v] - Wa[v], dlo[v]), Wb[v]);
   }
+  if constexpr (RECON == RECON_CHARACTERISTIC) {  // plane z0's slope from its own waves
+    float da[5], s0[5];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) da[v] = Wb[v] - Wa[v];
+    char_slope_f32<3>(Wb, da, dlo, g32, s0);
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) zp[v] = __builtin_fmaf(0.5f, s0[v], Wb[v]);
+  }
   // z face above plane j: primitives of plane j+2 (loaded one iteration
   // earlier), then the minus state of plane j+1 and HLLC with the carried plus
   // state of plane j
   auto zface = [&](float (&fz)[5]) {
     if (active) prims(Ud, Wd, true);
     float zr[5];
+    if constexpr (RECON == RECON_CHARACTERISTIC) {
+      float dhi[5], sc[5];
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) {
-      const float dhi = Wd[v] - Wc[v];
-      const float m = minmod_f(dlo[v], dhi);
-      zr[v] = __builtin_fmaf(-0.5f, m, Wc[v]);
-      dlo[v] = dhi;
-      Wa[v] = __builtin_fmaf(0.5f, m, Wc[v]);  // plus state of plane j+1, carried into zp
+      for (int v = 0; v < NVAR; ++v) dhi[v] = Wd[v] - Wc[v];
+      char_slope_f32<3>(Wc, dlo, dhi, g32, sc);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        zr[v] = __builtin_fmaf(-0.5f, sc[v], Wc[v]);
+        dlo[v] = dhi[v];
+        Wa[v] = __builtin_fmaf(0.5f, sc[v], Wc[v]);  // plus state of plane j+1, carried into zp
+      }
+      if (!(zp[0] > 0.0f && zp[4] > 0.0f && zr[0] > 0.0f && zr[4] > 0.0f) && active) {
+        bad = 1;
+        badblk = min(badblk, C.b);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const float dhi = Wd[v] - Wc[v];
+        const float m = minmod_f(dlo[v], dhi);
+        zr[v] = __builtin_fmaf(-0.5f, m, Wc[v]);
+        dlo[v] = dhi;
+        Wa[v] = __builtin_fmaf(0.5f, m, Wc[v]);  // plus state of plane j+1, carried into zp
+      }
     }
     float zl[5] = {zp[0], zp[1], zp[2], zp[3], zp[4]};  // zp is carried on as it is
     face_prims(zl);
@@ -1215,8 +1399,14 @@ static hipError_t launch_kr(int kmask, int speeds, int grid, hipStream_t s, cons
 
 template <int DIM, bool MIXED, int STAGE>
 static hipError_t launch_k(int kmask, int speeds, int recon, int grid, hipStream_t s, const StageArgs &a) {
-  return recon == RECON_CONSERVED ? launch_kr<DIM, MIXED, STAGE, RECON_CONSERVED>(kmask, speeds, grid, s, a)
-                                  : launch_kr<DIM, MIXED, STAGE, RECON_PRIMITIVE>(kmask, speeds, grid, s, a);
+  switch (recon) {
+    case RECON_CONSERVED:
+      return launch_kr<DIM, MIXED, STAGE, RECON_CONSERVED>(kmask, speeds, grid, s, a);
+    case RECON_CHARACTERISTIC:
+      return launch_kr<DIM, MIXED, STAGE, RECON_CHARACTERISTIC>(kmask, speeds, grid, s, a);
+    default:
+      return launch_kr<DIM, MIXED, STAGE, RECON_PRIMITIVE>(kmask, speeds, grid, s, a);
+  }
 }
 
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,

@@ -1,6 +1,7 @@
 """GPU parity of the method variants -- HLLC wave-speed bounds
 (HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS) and PLM on conserved variables
-(HYDRO_RECON_CONSERVED, alone and with Einfeldt bounds) -- against the oracle
+(HYDRO_RECON_CONSERVED, alone and with Einfeldt bounds) and on characteristic
+variables (HYDRO_RECON_CHARACTERISTIC, alone and with PVRS bounds) -- against the oracle
 run with the same options, through the C ABI: FP64 <= 1e-12 relative per cell
 (floored), mixed L1(rho) <= 1e-5 on smooth flow; uniform states bitwise;
 conservation on a periodic blast; the host-resident packet path with each
@@ -23,6 +24,8 @@ VARIANTS = {
     "pvrs": (H.PVRS, dict(speeds=O.PVRS)),
     "conserved": (H.CONSERVED, dict(recon=O.CONSERVED)),
     "conserved-einfeldt": (H.CONSERVED | H.EINFELDT, dict(speeds=O.EINFELDT, recon=O.CONSERVED)),
+    "characteristic": (H.CHARACTERISTIC, dict(recon=O.CHARACTERISTIC)),
+    "characteristic-pvrs": (H.CHARACTERISTIC | H.PVRS, dict(speeds=O.PVRS, recon=O.CHARACTERISTIC)),
 }
 
 
