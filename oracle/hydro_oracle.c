@@ -14,7 +14,9 @@
  *   - Sec. 5.1 (Flash-X): the domain is split into blocks that all hold the
  *     same number of equally sized cells;
  *   - Sec. 5.2 (Sedov blast wave): the only other physics is the ideal-gas
- *     gamma-law equation of state;
+ *     gamma-law equation of state (a gas + radiation EOS, iterated like the
+ *     heavier tabulated one of the paper's other application, is a method
+ *     variant here);
  *   - Sec. 6 (Experiments): the hydro solver is an explicit finite-volume
  *     method whose guard cells form a halo around the block being updated,
  *     integrated with a 2nd-order Runge-Kutta method that refreshes the
@@ -71,6 +73,7 @@ enum { ORACLE_NBR = 0, ORACLE_OUTFLOW = 1, ORACLE_PERIODIC_SELF = 2 };
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 3, ORACLE_ENONPHYS = 4 };
 enum { ORACLE_SPEEDS_DAVIS = 0, ORACLE_SPEEDS_EINFELDT = 1, ORACLE_SPEEDS_PVRS = 2 };
 enum { ORACLE_RECON_PRIMITIVE = 0, ORACLE_RECON_CONSERVED = 1, ORACLE_RECON_CHARACTERISTIC = 2 };
+enum { ORACLE_EOS_IDEAL = 0, ORACLE_EOS_GAS_RADIATION = 1 };
 
 typedef struct {
   int32_t nblocks;
@@ -82,6 +85,7 @@ typedef struct {
   const int64_t *offset; /* [nblocks] element offset of variable 0 in the arena */
   int32_t speeds;        /* HLLC wave-speed bounds: ORACLE_SPEEDS_DAVIS, _EINFELDT or _PVRS */
   int32_t recon;         /* PLM variables: ORACLE_RECON_PRIMITIVE, _CONSERVED or _CHARACTERISTIC */
+  int32_t eos;           /* ORACLE_EOS_IDEAL or ORACLE_EOS_GAS_RADIATION */
 } oracle_mesh;
 
 /* ------------------------------------------------------------------------ */
@@ -178,6 +182,83 @@ static int prim_ok(const double *W) {
   return W[0] > 0.0 && W[4] > 0.0;
 }
 
+/*
+ * Gas + radiation equation of state, a method variant standing in for a
+ * heavier (iterated) EOS: an ideal gas of adiabatic index gamma in
+ * equilibrium with black-body radiation, in units where the gas constant and
+ * the radiation constant are 1:
+ *     p = rho T + T^4 / 3,        rho e = rho T / (gamma - 1) + T^4.
+ * The temperature is the root of a convex increasing quartic, found by
+ * Newton's method from an upper bound (the smaller of the gas-only and the
+ * radiation-only temperature), so the iterates decrease monotonically; the
+ * iteration stops when an iterate no longer decreases.  The sound speed is
+ * c^2 = Gamma1 p / rho with the first adiabatic exponent of the mixture
+ * (Clayton 1968), beta = rho T / p the gas share of the pressure:
+ *     Gamma1 = beta + (4 - 3 beta)^2 (gamma - 1) / (beta + 12 (gamma - 1)(1 - beta)).
+ */
+#define ORACLE_ARAD 1.0
+
+double oracle_gr_temperature_e(double rho, double rhoe, double gamma) {
+  double cv = rho / (gamma - 1.0); /* rho c_v */
+  double T = fmin(rhoe / cv, sqrt(sqrt(rhoe / ORACLE_ARAD)));
+  for (int k = 0; k < 64; ++k) {
+    double T3 = T * T * T;
+    double f = cv * T + ORACLE_ARAD * T3 * T - rhoe;
+    double fp = cv + 4.0 * ORACLE_ARAD * T3;
+    double Tn = T - f / fp;
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
+double oracle_gr_temperature_p(double rho, double p) {
+  double T = fmin(p / rho, sqrt(sqrt(3.0 * p / ORACLE_ARAD)));
+  for (int k = 0; k < 64; ++k) {
+    double T3 = T * T * T;
+    double f = rho * T + ORACLE_ARAD * T3 * T / 3.0 - p;
+    double fp = rho + 4.0 * ORACLE_ARAD * T3 / 3.0;
+    double Tn = T - f / fp;
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
+double oracle_gr_gamma1(double rho, double T, double p, double gamma) {
+  double beta = rho * T / p;
+  double g1 = gamma - 1.0;
+  return beta + (4.0 - 3.0 * beta) * (4.0 - 3.0 * beta) * g1 / (beta + 12.0 * g1 * (1.0 - beta));
+}
+
+/* Conserved -> primitive under either EOS (the ideal one is oracle_prim).
+ * Gas + radiation: p from the temperature of rho e = E - m.u/2; a state with
+ * rho e <= 0 has no temperature and gets p = rho e (non-physical). */
+void oracle_prim_eos(const double *U, double gamma, int eos, double *W) {
+  oracle_prim(U, gamma, W);
+  if (eos == ORACLE_EOS_GAS_RADIATION) {
+    double rhoe = U[4] - 0.5 * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]);
+    if (!(rhoe > 0.0)) {
+      W[4] = rhoe;
+      return;
+    }
+    double T = oracle_gr_temperature_e(U[0], rhoe, gamma);
+    W[4] = U[0] * T + ORACLE_ARAD * T * T * T * T / 3.0;
+  }
+}
+
+/* Sound speed and internal energy per volume of primitive state W. */
+void oracle_thermo(const double *W, double gamma, int eos, double *c, double *rhoe) {
+  if (eos == ORACLE_EOS_GAS_RADIATION) {
+    double T = oracle_gr_temperature_p(W[0], W[4]);
+    *c = sqrt(oracle_gr_gamma1(W[0], T, W[4], gamma) * W[4] / W[0]);
+    *rhoe = W[0] * T / (gamma - 1.0) + ORACLE_ARAD * T * T * T * T;
+  } else {
+    *c = sqrt(gamma * W[4] / W[0]);
+    *rhoe = W[4] / (gamma - 1.0);
+  }
+}
+
 /* minmod limiter (Roe 1986): the argument of smaller magnitude when both have
  * the same strict sign, else zero.  Signs are tested directly (no a*b). */
 double oracle_minmod(double a, double b) {
@@ -241,17 +322,17 @@ static void char_slope(const double *W, const double *da, const double *db, doub
  *     W_2 - slope_2 / 2.
  * With the last two a non-physical face state (rho <= 0, p <= 0,
  * non-finite) is an error as well.  Returns ORACLE_OK or ORACLE_ENONPHYS. */
-int oracle_face_states(const double *u, double gamma, int recon, int dir, double *wl, double *wr) {
+static int face_states_eos(const double *u, double gamma, int recon, int eos, int dir, double *wl, double *wr) {
   double w[4][NVAR];
   for (int s = 0; s < 4; ++s) {
-    oracle_prim(u + s * NVAR, gamma, w[s]);
+    oracle_prim_eos(u + s * NVAR, gamma, eos, w[s]);
     if (!prim_ok(w[s])) return ORACLE_ENONPHYS;
   }
   if (recon == ORACLE_RECON_CONSERVED) {
     double ul[NVAR], ur[NVAR];
     oracle_plm_face(u, ul, ur);
-    oracle_prim(ul, gamma, wl);
-    oracle_prim(ur, gamma, wr);
+    oracle_prim_eos(ul, gamma, eos, wl);
+    oracle_prim_eos(ur, gamma, eos, wr);
   } else if (recon == ORACLE_RECON_CHARACTERISTIC) {
     double d01[NVAR], d12[NVAR], d23[NVAR], s1[NVAR], s2[NVAR];
     for (int v = 0; v < NVAR; ++v) {
@@ -273,6 +354,10 @@ int oracle_face_states(const double *u, double gamma, int recon, int dir, double
   return ORACLE_OK;
 }
 
+int oracle_face_states(const double *u, double gamma, int recon, int dir, double *wl, double *wr) {
+  return face_states_eos(u, gamma, recon, ORACLE_EOS_IDEAL, dir, wl, wr);
+}
+
 /*
  * Bounds S = (S_L, S_R) of the wave speeds of the Riemann problem at a face
  * whose normal is the first velocity component, c_K = sqrt(gamma p_K / rho_K).
@@ -291,11 +376,10 @@ int oracle_face_states(const double *u, double gamma, int recon, int dir, double
  *       shock factor q_K = sqrt(1 + (gamma + 1)/(2 gamma) (p* / p_K - 1));
  *     S_L = u_L - c_L q_L, S_R = u_R + c_R q_R.
  */
-void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int speeds, double *S) {
+static void wave_speeds_c(const double *WL, const double *WR, double cL, double cR, double gamma, int speeds,
+                          double *S) {
   double rL = WL[0], uL = WL[1], pL = WL[4];
   double rR = WR[0], uR = WR[1], pR = WR[4];
-  double cL = sqrt(gamma * pL / rL);
-  double cR = sqrt(gamma * pR / rR);
   if (speeds == ORACLE_SPEEDS_EINFELDT) {
     double sL = sqrt(rL), sR = sqrt(rR);
     double ubar = (sL * uL + sR * uR) / (sL + sR);
@@ -320,12 +404,20 @@ void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int sp
   }
 }
 
+void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int speeds, double *S) {
+  double cL = sqrt(gamma * WL[4] / WL[0]);
+  double cR = sqrt(gamma * WR[4] / WR[0]);
+  wave_speeds_c(WL, WR, cL, cR, gamma, speeds, S);
+}
+
 /*
  * HLLC flux across a face whose normal is the first velocity component
  * (Toro 2009, sec. 10.4-10.6; Toro, Spruce & Speares 1994).
  * WL, WR = (rho, u_normal, u_t1, u_t2, p).  F = (mass, normal momentum,
  * t1 momentum, t2 momentum, energy) flux in the same frame.
- *   Wave speeds S_L, S_R: oracle_wave_speeds (Davis, Einfeldt or PVRS).
+ *   Wave speeds S_L, S_R: oracle_wave_speeds (Davis, Einfeldt or PVRS), with
+ *   the sound speeds and E_K = rho e_K + rho_K |v_K|^2 / 2 of the EOS
+ *   (oracle_thermo).
  *   Contact speed: S* = [p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)]
  *                       / [rho_L (S_L - u_L) - rho_R (S_R - u_R)].
  *   Star states:   U*_K = rho_K (S_K - u_K)/(S_K - S*) *
@@ -335,14 +427,17 @@ void oracle_wave_speeds(const double *WL, const double *WR, double gamma, int sp
  *          F_R + S_R (U*_R - U_R) if S* < 0 < S_R
  *          F_R                    if S_R <= 0.
  */
-void oracle_hllc_speeds(const double *WL, const double *WR, double gamma, int speeds, double *F) {
+void oracle_hllc_eos(const double *WL, const double *WR, double gamma, int speeds, int eos, double *F) {
   double rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
   double rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
-  double EL = pL / (gamma - 1.0) + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
-  double ER = pR / (gamma - 1.0) + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
+  double cL, cR, eL, eR;
+  oracle_thermo(WL, gamma, eos, &cL, &eL);
+  oracle_thermo(WR, gamma, eos, &cR, &eR);
+  double EL = eL + 0.5 * rL * (uL * uL + vL * vL + wL * wL);
+  double ER = eR + 0.5 * rR * (uR * uR + vR * vR + wR * wR);
 
   double S[2];
-  oracle_wave_speeds(WL, WR, gamma, speeds, S);
+  wave_speeds_c(WL, WR, cL, cR, gamma, speeds, S);
   double SL = S[0], SR = S[1];
   double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
 
@@ -366,14 +461,20 @@ void oracle_hllc_speeds(const double *WL, const double *WR, double gamma, int sp
   }
 }
 
+/* HLLC with the ideal-gas EOS. */
+void oracle_hllc_speeds(const double *WL, const double *WR, double gamma, int speeds, double *F) {
+  oracle_hllc_eos(WL, WR, gamma, speeds, ORACLE_EOS_IDEAL, F);
+}
+
 /* HLLC with Davis wave speeds. */
 void oracle_hllc(const double *WL, const double *WR, double gamma, double *F) {
   oracle_hllc_speeds(WL, WR, gamma, ORACLE_SPEEDS_DAVIS, F);
 }
 
 /* Local CFL rate of one cell: sum over active directions of (|u_d| + c)/dx_d. */
-static double cell_lambda(const double *W, double gamma, const double *dx, int ndim) {
-  double c = sqrt(gamma * W[4] / W[0]);
+static double cell_lambda(const double *W, double gamma, int eos, const double *dx, int ndim) {
+  double c, rhoe;
+  oracle_thermo(W, gamma, eos, &c, &rhoe);
   double lam = 0.0;
   for (int d = 0; d < ndim; ++d) lam += (fabs(W[1 + d]) + c) / dx[d];
   return lam;
@@ -426,7 +527,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
             for (int v = 0; v < NVAR; ++v) u[s][v] = S.q[pidx(&S, v, c[0], c[1], c[2])];
           }
           double wl[NVAR], wr[NVAR], rl[NVAR], rr[NVAR], f[NVAR];
-          rc = oracle_face_states(&u[0][0], gamma, m->recon, d, wl, wr);
+          rc = face_states_eos(&u[0][0], gamma, m->recon, m->eos, d, wl, wr);
           if (rc) break;
           /* rotate: the normal velocity component goes into slot 1 */
           for (int v = 0; v < NVAR; ++v) {
@@ -437,7 +538,7 @@ static int block_stage(const oracle_mesh *m, int b, const double *Usrc, const do
           rl[1 + d] = wl[1];
           rr[1] = wr[1 + d];
           rr[1 + d] = wr[1];
-          oracle_hllc_speeds(rl, rr, gamma, m->speeds, f);
+          oracle_hllc_eos(rl, rr, gamma, m->speeds, m->eos, f);
           /* rotate back */
           double t = f[1];
           f[1] = f[1 + d];
@@ -490,6 +591,10 @@ int oracle_validate(const oracle_mesh *m) {
   if (m->nblocks > 0 && (!m->n || !m->dx || !m->kind || !m->nbr || !m->offset)) return ORACLE_EINVAL;
   if (m->speeds < ORACLE_SPEEDS_DAVIS || m->speeds > ORACLE_SPEEDS_PVRS) return ORACLE_EINVAL;
   if (m->recon < ORACLE_RECON_PRIMITIVE || m->recon > ORACLE_RECON_CHARACTERISTIC) return ORACLE_EINVAL;
+  if (m->eos != ORACLE_EOS_IDEAL && m->eos != ORACLE_EOS_GAS_RADIATION) return ORACLE_EINVAL;
+  /* the wave-speed and reconstruction variants assume the gamma-law EOS */
+  if (m->eos == ORACLE_EOS_GAS_RADIATION && (m->speeds != ORACLE_SPEEDS_DAVIS || m->recon != ORACLE_RECON_PRIMITIVE))
+    return ORACLE_EINVAL;
   for (int b = 0; b < m->nblocks; ++b) {
     const int32_t *n = m->n + 3 * b;
     if (m->ndim == 2 && n[2] != 1) return ORACLE_EINVAL;
@@ -528,12 +633,12 @@ int oracle_max_lambda(const oracle_mesh *m, const double *U, double gamma, doubl
         for (int i = 0; i < n[0]; ++i) {
           double u[NVAR], w[NVAR];
           for (int v = 0; v < NVAR; ++v) u[v] = U[aidx(m, b, v, i, j, k)];
-          oracle_prim(u, gamma, w);
+          oracle_prim_eos(u, gamma, m->eos, w);
           if (!prim_ok(w)) {
             bad = 1;
             continue;
           }
-          double l = cell_lambda(w, gamma, m->dx + 3 * b, m->ndim);
+          double l = cell_lambda(w, gamma, m->eos, m->dx + 3 * b, m->ndim);
           if (l > lam) lam = l;
         }
   }

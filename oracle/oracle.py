@@ -24,6 +24,7 @@ _OVERRIDE = os.environ.get("HYDRO_ORACLE_LIB")
 OK, EINVAL, ENOMEM, ENONPHYS = 0, 1, 3, 4
 DAVIS, EINFELDT, PVRS = 0, 1, 2  # HLLC wave-speed bounds
 PRIMITIVE, CONSERVED, CHARACTERISTIC = 0, 1, 2  # variables PLM reconstructs
+IDEAL, GAS_RADIATION = 0, 1  # equations of state
 
 
 class OracleError(RuntimeError):
@@ -43,6 +44,7 @@ class _Mesh(C.Structure):
         ("offset", C.POINTER(C.c_int64)),
         ("speeds", C.c_int32),
         ("recon", C.c_int32),
+        ("eos", C.c_int32),
     ]
 
 
@@ -66,6 +68,15 @@ def lib():
         L.oracle_hllc.argtypes = [dp, dp, C.c_double, dp]
         L.oracle_hllc_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
         L.oracle_wave_speeds.argtypes = [dp, dp, C.c_double, C.c_int, dp]
+        L.oracle_hllc_eos.argtypes = [dp, dp, C.c_double, C.c_int, C.c_int, dp]
+        L.oracle_prim_eos.argtypes = [dp, C.c_double, C.c_int, dp]
+        L.oracle_thermo.argtypes = [dp, C.c_double, C.c_int, dp, dp]
+        L.oracle_gr_temperature_e.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_gr_temperature_e.restype = C.c_double
+        L.oracle_gr_temperature_p.argtypes = [C.c_double, C.c_double]
+        L.oracle_gr_temperature_p.restype = C.c_double
+        L.oracle_gr_gamma1.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_gr_gamma1.restype = C.c_double
         L.oracle_validate.argtypes = [mp]
         L.oracle_max_lambda.argtypes = [mp, dp, C.c_double, dp]
         L.oracle_step.argtypes = [mp, dp, C.c_double, C.c_double]
@@ -85,7 +96,7 @@ def _dptr(a: np.ndarray):
 class _MeshArgs:
     """Keeps the contiguous copies alive while the C struct points at them."""
 
-    def __init__(self, mesh, speeds: int = DAVIS, recon: int = PRIMITIVE):
+    def __init__(self, mesh, speeds: int = DAVIS, recon: int = PRIMITIVE, eos: int = IDEAL):
         self.n = np.ascontiguousarray(mesh.n, dtype=np.int32)
         self.dx = np.ascontiguousarray(mesh.dx, dtype=np.float64)
         self.kind = np.ascontiguousarray(mesh.kind, dtype=np.int32)
@@ -101,6 +112,7 @@ class _MeshArgs:
             self.offset.ctypes.data_as(C.POINTER(C.c_int64)),
             int(speeds),
             int(recon),
+            int(eos),
         )
 
     def ref(self):
@@ -142,16 +154,45 @@ def face_states(u4, gamma: float, recon: int = PRIMITIVE, direction: int = 0):
     return None if rc == ENONPHYS else (wl, wr)
 
 
-def hllc(WL, WR, gamma: float, speeds: int = DAVIS) -> np.ndarray:
+def hllc(WL, WR, gamma: float, speeds: int = DAVIS, eos: int = IDEAL) -> np.ndarray:
     """HLLC flux for states (rho, u_normal, u_t1, u_t2, p)."""
     a = np.ascontiguousarray(WL, dtype=np.float64)
     b = np.ascontiguousarray(WR, dtype=np.float64)
     f = np.empty(5)
-    if speeds == DAVIS:
+    if speeds == DAVIS and eos == IDEAL:
         lib().oracle_hllc(_dptr(a), _dptr(b), gamma, _dptr(f))
-    else:
+    elif eos == IDEAL:
         lib().oracle_hllc_speeds(_dptr(a), _dptr(b), gamma, int(speeds), _dptr(f))
+    else:
+        lib().oracle_hllc_eos(_dptr(a), _dptr(b), gamma, int(speeds), int(eos), _dptr(f))
     return f
+
+
+def prim_eos(U, gamma: float, eos: int = IDEAL) -> np.ndarray:
+    u = np.ascontiguousarray(U, dtype=np.float64)
+    w = np.empty(5)
+    lib().oracle_prim_eos(_dptr(u), gamma, int(eos), _dptr(w))
+    return w
+
+
+def thermo(W, gamma: float, eos: int = IDEAL) -> tuple[float, float]:
+    """(sound speed, internal energy per volume) of primitive state W."""
+    w = np.ascontiguousarray(W, dtype=np.float64)
+    c, e = C.c_double(), C.c_double()
+    lib().oracle_thermo(_dptr(w), gamma, int(eos), C.byref(c), C.byref(e))
+    return c.value, e.value
+
+
+def gr_temperature_e(rho: float, rhoe: float, gamma: float) -> float:
+    return lib().oracle_gr_temperature_e(rho, rhoe, gamma)
+
+
+def gr_temperature_p(rho: float, p: float) -> float:
+    return lib().oracle_gr_temperature_p(rho, p)
+
+
+def gr_gamma1(rho: float, T: float, p: float, gamma: float) -> float:
+    return lib().oracle_gr_gamma1(rho, T, p, gamma)
 
 
 def wave_speeds(WL, WR, gamma: float, speeds: int = DAVIS) -> tuple[float, float]:
@@ -164,33 +205,34 @@ def wave_speeds(WL, WR, gamma: float, speeds: int = DAVIS) -> tuple[float, float
 
 
 # ------------------------------------------------------------------- mesh
-def validate(mesh, speeds: int = DAVIS, recon: int = PRIMITIVE) -> int:
-    m = _MeshArgs(mesh, speeds, recon)
+def validate(mesh, speeds: int = DAVIS, recon: int = PRIMITIVE, eos: int = IDEAL) -> int:
+    m = _MeshArgs(mesh, speeds, recon, eos)
     return lib().oracle_validate(m.ref())
 
 
-def max_lambda(mesh, U: np.ndarray, gamma: float) -> float:
-    m = _MeshArgs(mesh)
+def max_lambda(mesh, U: np.ndarray, gamma: float, eos: int = IDEAL) -> float:
+    m = _MeshArgs(mesh, eos=eos)
     out = C.c_double(0.0)
     _check(lib().oracle_max_lambda(m.ref(), _dptr(U), gamma, C.byref(out)), "max_lambda")
     return out.value
 
 
-def dt(mesh, U: np.ndarray, gamma: float, cfl: float) -> float:
-    return cfl / max_lambda(mesh, U, gamma)
+def dt(mesh, U: np.ndarray, gamma: float, cfl: float, eos: int = IDEAL) -> float:
+    return cfl / max_lambda(mesh, U, gamma, eos)
 
 
-def step(mesh, U: np.ndarray, dt_: float, gamma: float, speeds: int = DAVIS, recon: int = PRIMITIVE) -> None:
+def step(mesh, U: np.ndarray, dt_: float, gamma: float, speeds: int = DAVIS, recon: int = PRIMITIVE,
+         eos: int = IDEAL) -> None:
     """One SSP-RK2 step of the whole mesh, in place."""
-    m = _MeshArgs(mesh, speeds, recon)
+    m = _MeshArgs(mesh, speeds, recon, eos)
     _check(lib().oracle_step(m.ref(), _dptr(U), dt_, gamma), "step")
 
 
 def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: int = DAVIS,
-                recon: int = PRIMITIVE) -> np.ndarray:
+                recon: int = PRIMITIVE, eos: int = IDEAL) -> np.ndarray:
     """One step for the listed blocks; returns a copy of U whose target blocks
     hold the new state (other blocks unchanged)."""
-    m = _MeshArgs(mesh, speeds, recon)
+    m = _MeshArgs(mesh, speeds, recon, eos)
     t = np.ascontiguousarray(targets, dtype=np.int32)
     out = U.copy()
     _check(lib().oracle_step_subset(m.ref(), _dptr(U), dt_, gamma, t.ctypes.data_as(C.POINTER(C.c_int32)),
@@ -199,9 +241,9 @@ def step_subset(mesh, U: np.ndarray, dt_: float, gamma: float, targets, speeds: 
 
 
 def run(mesh, U: np.ndarray, nsteps: int, cfl: float, gamma: float, fixed_dt: float = 0.0,
-        speeds: int = DAVIS, recon: int = PRIMITIVE):
+        speeds: int = DAVIS, recon: int = PRIMITIVE, eos: int = IDEAL):
     """nsteps steps in place; returns (dts array, t)."""
-    m = _MeshArgs(mesh, speeds, recon)
+    m = _MeshArgs(mesh, speeds, recon, eos)
     dts = np.zeros(max(nsteps, 1))
     t = C.c_double(0.0)
     _check(lib().oracle_run(m.ref(), _dptr(U), int(nsteps), cfl, gamma, fixed_dt, _dptr(dts), C.byref(t)), "run")

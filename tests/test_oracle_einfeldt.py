@@ -172,15 +172,16 @@ def test_scheme_with_einfeldt_speeds_converges_on_sod():
     assert not np.array_equal(sod_l1(64, E)[1], sod_l1(64, O.DAVIS)[1])
 
 
-def check_scheme_invariants(E, recon=O.PRIMITIVE):
+def check_scheme_invariants(E, recon=O.PRIMITIVE, eos=O.IDEAL):
     """Uniform state, conservation and blast mirror symmetry of the whole
-    scheme with wave-speed option E and reconstruction option recon."""
+    scheme with wave-speed option E, reconstruction option recon and
+    equation of state eos."""
     gamma = 1.4
     # uniform state: bitwise fixed point
     mesh = I.block_grid((2, 1, 2), (8, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
     U0 = I.uniform_state(mesh, gamma=gamma)
     U = U0.copy()
-    O.run(mesh, U, 4, 0.4, gamma, speeds=E, recon=recon)
+    O.run(mesh, U, 4, 0.4, gamma, speeds=E, recon=recon, eos=eos)
     assert np.array_equal(U, U0)
     # conservation on a periodic mesh with a strong pulse
     mesh = I.block_grid((2, 2, 2), (8, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
@@ -190,7 +191,7 @@ def check_scheme_invariants(E, recon=O.PRIMITIVE):
     vol = float(np.prod(mesh.dx[0]))
     t0 = [math.fsum(U.reshape(mesh.nblocks, 5, -1)[:, v].ravel()) * vol for v in range(5)]
     s0 = [math.fsum(np.abs(U.reshape(mesh.nblocks, 5, -1)[:, v].ravel())) * vol for v in range(5)]
-    O.run(mesh, U, 10, 0.4, gamma, speeds=E, recon=recon)
+    O.run(mesh, U, 10, 0.4, gamma, speeds=E, recon=recon, eos=eos)
     for v in range(5):
         t1 = math.fsum(U.reshape(mesh.nblocks, 5, -1)[:, v].ravel()) * vol
         assert abs(t1 - t0[v]) <= 1e-13 * s0[v] * 10
@@ -198,7 +199,7 @@ def check_scheme_invariants(E, recon=O.PRIMITIVE):
     prims = I.grid_field(mesh, lambda x, y, z: (1.0, 0.0, 0.0, 0.0, 1e-3))
     I.sedov_deposit(mesh, prims, 1.0, 2.0, (0.5, 0.5, 0.5), gamma)
     U = I.conserved_arena(mesh, prims, gamma)
-    O.run(mesh, U, 6, 0.4, gamma, speeds=E, recon=recon)
+    O.run(mesh, U, 6, 0.4, gamma, speeds=E, recon=recon, eos=eos)
     for axis in range(3):
         ax = 2 - axis
         for v in range(5):

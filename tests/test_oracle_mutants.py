@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
 PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py",
-        "tests/test_oracle_pvrs.py", "tests/test_oracle_recon.py"]
+        "tests/test_oracle_pvrs.py", "tests/test_oracle_recon.py", "tests/test_oracle_eos.py"]
 
 MUTANTS = {
     "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
@@ -56,6 +56,18 @@ MUTANTS = {
     "char-velocity-back-factor": ("s[n] = (c / W[0]) * (ap - am);", "s[n] = (c * W[0]) * (ap - am);"),
     "char-normal-index": ("int n = 1 + dir,", "int n = 1,"),
     "char-right-slope-cell": ("char_slope(w[2], d12, d23, gamma, dir, s2);", "char_slope(w[1], d12, d23, gamma, dir, s2);"),
+    "eos-gamma1-numerator": ("(4.0 - 3.0 * beta) * (4.0 - 3.0 * beta) * g1", "(4.0 - 2.0 * beta) * (4.0 - 3.0 * beta) * g1"),
+    "eos-radiation-energy-as-pressure": ("double f = cv * T + ORACLE_ARAD * T3 * T - rhoe;",
+                                         "double f = cv * T + ORACLE_ARAD * T3 * T / 3.0 - rhoe;"),
+    "eos-newton-derivative": ("double fp = cv + 4.0 * ORACLE_ARAD * T3;", "double fp = cv + 3.0 * ORACLE_ARAD * T3;"),
+    "eos-prim-radiation-pressure": ("W[4] = U[0] * T + ORACLE_ARAD * T * T * T * T / 3.0;",
+                                    "W[4] = U[0] * T + ORACLE_ARAD * T * T * T * T;"),
+    "eos-sound-uses-gamma": ("*c = sqrt(oracle_gr_gamma1(W[0], T, W[4], gamma) * W[4] / W[0]);",
+                             "*c = sqrt(gamma * W[4] / W[0]);"),
+    "eos-step-hllc-ideal": ("oracle_hllc_eos(rl, rr, gamma, m->speeds, m->eos, f);",
+                            "oracle_hllc_eos(rl, rr, gamma, m->speeds, ORACLE_EOS_IDEAL, f);"),
+    "eos-cfl-ideal": ("double l = cell_lambda(w, gamma, m->eos, m->dx + 3 * b, m->ndim);",
+                      "double l = cell_lambda(w, gamma, ORACLE_EOS_IDEAL, m->dx + 3 * b, m->ndim);"),
 }
 
 
