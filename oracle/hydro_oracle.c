@@ -167,12 +167,16 @@ static void pblock_load(pblock *B, const oracle_mesh *m, int b, const double *U)
 
 /* Conserved -> primitive with the ideal-gas gamma-law EOS (Sec. 5.2):
  * u_d = m_d / rho;  rho*e = E - (m_x u + m_y v + m_z w)/2;  p = (gamma-1) rho*e. */
-void oracle_prim(const double *U, double gamma, double *W) {
+static double velocities_and_rhoe(const double *U, double *W) {
   W[0] = U[0];
   W[1] = U[1] / U[0];
   W[2] = U[2] / U[0];
   W[3] = U[3] / U[0];
-  double rhoe = U[4] - 0.5 * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]);
+  return U[4] - 0.5 * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]);
+}
+
+void oracle_prim(const double *U, double gamma, double *W) {
+  double rhoe = velocities_and_rhoe(U, W);
   W[4] = (gamma - 1.0) * rhoe;
 }
 
@@ -235,16 +239,17 @@ double oracle_gr_gamma1(double rho, double T, double p, double gamma) {
  * Gas + radiation: p from the temperature of rho e = E - m.u/2; a state with
  * rho e <= 0 has no temperature and gets p = rho e (non-physical). */
 void oracle_prim_eos(const double *U, double gamma, int eos, double *W) {
-  oracle_prim(U, gamma, W);
-  if (eos == ORACLE_EOS_GAS_RADIATION) {
-    double rhoe = U[4] - 0.5 * (U[1] * W[1] + U[2] * W[2] + U[3] * W[3]);
-    if (!(rhoe > 0.0)) {
-      W[4] = rhoe;
-      return;
-    }
-    double T = oracle_gr_temperature_e(U[0], rhoe, gamma);
-    W[4] = U[0] * T + ORACLE_ARAD * T * T * T * T / 3.0;
+  if (eos != ORACLE_EOS_GAS_RADIATION) {
+    oracle_prim(U, gamma, W);
+    return;
   }
+  double rhoe = velocities_and_rhoe(U, W);
+  if (!(rhoe > 0.0)) {
+    W[4] = rhoe;
+    return;
+  }
+  double T = oracle_gr_temperature_e(U[0], rhoe, gamma);
+  W[4] = U[0] * T + ORACLE_ARAD * T * T * T * T / 3.0;
 }
 
 /* Sound speed and internal energy per volume of primitive state W. */

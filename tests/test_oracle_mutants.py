@@ -38,8 +38,8 @@ MUTANTS = {
     "einfeldt-density-weights": ("double ubar = (sL * uL + sR * uR) / (sL + sR);",
                                  "double ubar = (rL * uL + rR * uR) / (rL + rR);"),
     "einfeldt-unweighted-c2": ("(sL * cL * cL + sR * cR * cR) / (sL + sR)", "(cL * cL + cR * cR) / 2.0"),
-    "einfeldt-step-uses-davis": ("oracle_hllc_speeds(rl, rr, gamma, m->speeds, f);",
-                                 "oracle_hllc_speeds(rl, rr, gamma, ORACLE_SPEEDS_DAVIS, f);"),
+    "einfeldt-step-uses-davis": ("oracle_hllc_eos(rl, rr, gamma, m->speeds, m->eos, f);",
+                                 "oracle_hllc_eos(rl, rr, gamma, ORACLE_SPEEDS_DAVIS, m->eos, f);"),
     "pvrs-jump-sign": ("0.5 * (pL + pR) - 0.5 * (uR - uL)", "0.5 * (pL + pR) + 0.5 * (uR - uL)"),
     "pvrs-impedance-left-only": ("double rbar = 0.5 * (rL + rR)", "double rbar = rL"),
     "pvrs-shock-factor": ("double k = (gamma + 1.0) / (2.0 * gamma);", "double k = (gamma - 1.0) / (2.0 * gamma);"),
@@ -47,9 +47,9 @@ MUTANTS = {
     "pvrs-right-uses-left-sound": ("S[1] = uR + cR * qR;", "S[1] = uR + cL * qR;"),
     "recon-conserved-uses-primitives": ("    oracle_plm_face(u, ul, ur);", "    oracle_plm_face(&w[0][0], ul, ur);"),
     "recon-no-face-state-check": ("if (!prim_ok(wl) || !prim_ok(wr)) return ORACLE_ENONPHYS;", "(void)0;"),
-    "recon-right-state-from-left": ("    oracle_prim(ur, gamma, wr);", "    oracle_prim(ul, gamma, wr);"),
-    "recon-option-ignored": ("oracle_face_states(&u[0][0], gamma, m->recon, d, wl, wr);",
-                             "oracle_face_states(&u[0][0], gamma, ORACLE_RECON_PRIMITIVE, d, wl, wr);"),
+    "recon-right-state-from-left": ("    oracle_prim_eos(ur, gamma, eos, wr);", "    oracle_prim_eos(ul, gamma, eos, wr);"),
+    "recon-option-ignored": ("face_states_eos(&u[0][0], gamma, m->recon, m->eos, d, wl, wr);",
+                             "face_states_eos(&u[0][0], gamma, ORACLE_RECON_PRIMITIVE, m->eos, d, wl, wr);"),
     "char-impedance-sign": ("double ap = oracle_minmod((da[4] + rc * da[n])", "double ap = oracle_minmod((da[4] - rc * da[n])"),
     "char-entropy-drops-pressure": ("double a0 = oracle_minmod(da[0] - da[4] / c2, db[0] - db[4] / c2);",
                                     "double a0 = oracle_minmod(da[0], db[0] - db[4] / c2);"),
