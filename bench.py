@@ -316,14 +316,15 @@ def main():
                                             for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
 
-    # method variants (Einfeldt, PVRS wave speeds; conserved, characteristic PLM):
+    # method variants (Einfeldt, PVRS wave speeds; conserved, characteristic PLM; gas + radiation EOS):
     # kernel time of a few eager steps
     variants = {}
     for name, prec in (("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT), ("fp64_einfeldt", H.FP64 | H.EINFELDT),
                        ("mixed_pvrs", H.FP32_FP64 | H.PVRS), ("fp64_pvrs", H.FP64 | H.PVRS),
                        ("mixed_conserved", H.FP32_FP64 | H.CONSERVED), ("fp64_conserved", H.FP64 | H.CONSERVED),
                        ("mixed_characteristic", H.FP32_FP64 | H.CHARACTERISTIC),
-                       ("fp64_characteristic", H.FP64 | H.CHARACTERISTIC)):
+                       ("fp64_characteristic", H.FP64 | H.CHARACTERISTIC),
+                       ("fp64_gas_radiation", H.FP64 | H.GAS_RADIATION)):
         arena.copy_(U0_dev)
         b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
         k = b.time_kernels(min(args.steps, 5), P.cfl, P.gamma)
@@ -381,8 +382,8 @@ def main():
     km = kernel_ms["batched_mixed"]
     stage_ms = km["stage1_ms"] + km["stage2_ms"]
     achieved = BYTES_PER_CELL_UPDATE * cells / (stage_ms * 1e-3) / 1e9
-    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0, 0>(hyd::StageArgs)",
-                                "void hyd::k_stage<3, true, 2, 1, 0, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
+    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0, 0, 0>(hyd::StageArgs)",
+                                "void hyd::k_stage<3, true, 2, 1, 0, 0, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,

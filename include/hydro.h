@@ -103,6 +103,16 @@ typedef enum {
  * HYDRO_ENONPHYS as above. */
 #define HYDRO_RECON_CHARACTERISTIC 0x800
 
+/* Equation-of-state variant, only as HYDRO_FP64 | HYDRO_EOS_GAS_RADIATION
+ * (Davis bounds, primitive PLM; any other combination is EINVAL): an ideal
+ * gas of index gamma plus black-body radiation, in units with gas and
+ * radiation constants 1, p = rho T + T^4/3 and rho e = rho T/(gamma - 1) +
+ * T^4.  Every recovery, face state and CFL rate solves for the temperature by
+ * Newton's method, and the sound speed uses the first adiabatic exponent of
+ * the mixture (Clayton): a heavier, iterated EOS in the role of the paper's
+ * tabulated one (Sec. 5.3). */
+#define HYDRO_EOS_GAS_RADIATION 0x1000
+
 typedef enum {
   HYDRO_NBR = 0,          /* guards copy the two nearest interior layers of block nbr[f] */
   HYDRO_OUTFLOW = 1,      /* zero gradient: both guard layers copy the edge layer        */

@@ -392,23 +392,26 @@ int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.
 
 // A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
 // with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS and one of
-// HYDRO_RECON_CONSERVED, HYDRO_RECON_CHARACTERISTIC.
+// HYDRO_RECON_CONSERVED, HYDRO_RECON_CHARACTERISTIC; or HYDRO_FP64 with
+// HYDRO_EOS_GAS_RADIATION alone.
 bool prec_valid(int32_t p) {
   const int32_t base = p & 0xff, sp = p & (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS);
   const int32_t rc = p & (HYDRO_RECON_CONSERVED | HYDRO_RECON_CHARACTERISTIC);
   const int32_t rest = p & ~(0xff | HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS | HYDRO_RECON_CONSERVED |
-                             HYDRO_RECON_CHARACTERISTIC);
+                             HYDRO_RECON_CHARACTERISTIC | HYDRO_EOS_GAS_RADIATION);
+  if (p & HYDRO_EOS_GAS_RADIATION) return p == (HYDRO_FP64 | HYDRO_EOS_GAS_RADIATION);
   return rest == 0 && sp != (HYDRO_SPEEDS_EINFELDT | HYDRO_SPEEDS_PVRS) &&
          rc != (HYDRO_RECON_CONSERVED | HYDRO_RECON_CHARACTERISTIC) && (base == HYDRO_FP64 || base == HYDRO_FP32_FP64);
 }
 bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
 int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : (p & HYDRO_SPEEDS_PVRS) ? 2 : 0; }
 int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : (p & HYDRO_RECON_CHARACTERISTIC) ? 2 : 0; }
+int eos_of(int32_t p) { return (p & HYDRO_EOS_GAS_RADIATION) ? 1 : 0; }
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a) {
   hipError_t e = hyd::launch_stage(m->ndim, is_mixed(prec), stage, wl.kmask, speeds_of(prec), recon_of(prec),
-                                   grid_of(wl, grid), s, a);
+                                   eos_of(prec), grid_of(wl, grid), s, a);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return HYDRO_OK;
 }
@@ -572,7 +575,7 @@ hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, d
   if (!(p->lam_valid && p->lam_gamma == gamma)) {
     hipError_t e = hyd::launch_reset(p->d_time, m->stream);
     if (e == hipSuccess)
-      e = hyd::launch_lambda(m->ndim, p->wl.kmask, p->wl.nitems, m->stream,
+      e = hyd::launch_lambda(m->ndim, p->wl.kmask, eos_of(p->prec), p->wl.nitems, m->stream,
                              stage_args(m, p->wl, 1, 0.0, nullptr, p->d_time, gamma, 0));
     if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("rate launch: ") + hipGetErrorString(e));
   }
@@ -713,7 +716,7 @@ hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double 
   // dt of the first step from the current state
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
-    e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
+    e = hyd::launch_lambda(m->ndim, b->wl.kmask, eos_of(b->prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
@@ -736,7 +739,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   for (auto *p : b->packets) p->lam_valid = false;
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
-    e = hyd::launch_lambda(m->ndim, b->wl.kmask, grid_of(b->wl, b->grid), m->stream,
+    e = hyd::launch_lambda(m->ndim, b->wl.kmask, eos_of(prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
@@ -978,7 +981,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   for (int p = 0; p < np && good; ++p) {
     auto &sl = s->slots[s->pslot[p]];
     copy_in(p, sl);
-    good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, s->wl[p].nitems, sl.stream,
+    good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, eos_of(prec), s->wl[p].nitems, sl.stream,
                                          slot_args(s, sl, s->wl[p], 1, gamma)));
     if (p == lastp[s->pslot[p]]) done(sl);
   }
@@ -1000,7 +1003,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
       }
       for (int stage = 1; stage <= 2; ++stage)
         good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), stage, s->wl[p].kmask, speeds_of(prec),
-                                            recon_of(prec), s->wl[p].nitems, sl.stream,
+                                            recon_of(prec), eos_of(prec), s->wl[p].nitems, sl.stream,
                                             slot_args(s, sl, s->wl[p], stage, gamma)));
       if (p == lastp[k]) done(sl);
       good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),

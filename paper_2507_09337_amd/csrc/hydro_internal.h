@@ -69,9 +69,10 @@ struct StageArgs {
 // kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
 // speeds: 0 = Davis, 1 = Einfeldt, 2 = pressure-based (PVRS) wave-speed bounds in HLLC.
 // recon: 0 = PLM on primitives, 1 = on conserved variables, 2 = on characteristic variables.
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,
-                        const StageArgs &a);
-hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a);
+// eos: 0 = gamma law, 1 = gas + radiation (FP64 with Davis bounds and primitive PLM only).
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int eos, int grid,
+                        hipStream_t s, const StageArgs &a);
+hipError_t launch_lambda(int ndim, int kmask, int eos, int grid, hipStream_t s, const StageArgs &a);
 hipError_t launch_reset(DevTime *t, hipStream_t s);
 hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s);
 

@@ -80,6 +80,69 @@ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
 enum { SPEEDS_DAVIS = 0, SPEEDS_EINFELDT = 1, SPEEDS_PVRS = 2 };
 // Variables PLM reconstructs.
 enum { RECON_PRIMITIVE = 0, RECON_CONSERVED = 1, RECON_CHARACTERISTIC = 2 };
+// Equation of state: the gamma law, or gas + radiation (FP64 tile only).
+enum { EOS_IDEAL = 0, EOS_GAS_RADIATION = 1 };
+
+// Gas + radiation EOS in units with gas and radiation constants 1:
+//   p = rho T + T^4/3,  rho e = rho T/(gamma - 1) + T^4.
+// The temperature is the root of a convex increasing quartic, found by
+// Newton's method from an upper bound (the smaller of the gas-only and the
+// radiation-only temperature): the iterates decrease until one no longer
+// does.  First adiabatic exponent of the mixture (Clayton), beta = rho T / p:
+//   Gamma1 = beta + (4 - 3 beta)^2 (gamma - 1)/(beta + 12 (gamma - 1)(1 - beta)).
+// Plain FP64 in the order of the statement (IEEE division and square root),
+// so each result is rounded as in a CPU evaluation of the same formulas.
+constexpr double ARAD = 1.0;
+
+__device__ __forceinline__ double gr_temperature_e(double rho, double rhoe, double gamma) {
+#pragma clang fp contract(off)
+  const double cv = rho / (gamma - 1.0);
+  double T = fmin(rhoe / cv, __builtin_sqrt(__builtin_sqrt(rhoe / ARAD)));
+  for (int k = 0; k < 64; ++k) {
+    const double T3 = T * T * T;
+    const double f = cv * T + ARAD * T3 * T - rhoe;
+    const double fp = cv + 4.0 * ARAD * T3;
+    const double Tn = T - f / fp;
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
+__device__ __forceinline__ double gr_temperature_p(double rho, double p) {
+#pragma clang fp contract(off)
+  double T = fmin(p / rho, __builtin_sqrt(__builtin_sqrt(3.0 * p / ARAD)));
+  for (int k = 0; k < 64; ++k) {
+    const double T3 = T * T * T;
+    const double f = rho * T + ARAD * T3 * T / 3.0 - p;
+    const double fp = rho + 4.0 * ARAD * T3 / 3.0;
+    const double Tn = T - f / fp;
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
+__device__ __forceinline__ double gr_gamma1(double rho, double T, double p, double gamma) {
+#pragma clang fp contract(off)
+  const double beta = rho * T / p;
+  const double g1 = gamma - 1.0;
+  return beta + (4.0 - 3.0 * beta) * (4.0 - 3.0 * beta) * g1 / (beta + 12.0 * g1 * (1.0 - beta));
+}
+
+// Sound speed and internal energy per volume of a primitive state.
+template <int EOS>
+__device__ __forceinline__ void thermo_fp64(double r, double p, double g, double &c, double &e) {
+#pragma clang fp contract(off)
+  if constexpr (EOS == EOS_GAS_RADIATION) {
+    const double T = gr_temperature_p(r, p);
+    c = __builtin_sqrt(gr_gamma1(r, T, p, g) * p / r);
+    e = r * T / (g - 1.0) + ARAD * T * T * T * T;
+  } else {
+    c = __builtin_sqrt(g * p / r);
+    e = p / (g - 1.0);
+  }
+}
 
 // HLLC flux in the face frame: L, R = (rho, u_normal, u_t1, u_t2, p).  Wave
 // speed bounds: Davis, min/max of u -+ c over both sides; or Einfeldt,
@@ -168,13 +231,14 @@ __device__ __forceinline__ void hllc(const float L[5], const float R[5], float g
 // no contraction into FMAs.  Division and square root are IEEE-correct on the
 // device, so each face flux is rounded exactly as in a plain FP64 CPU
 // evaluation of the same formulas.  Only the side K of the contact is formed.
-template <int SPEEDS>
+template <int SPEEDS, int EOS = EOS_IDEAL>
 __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], double g, double F[5]) {
 #pragma clang fp contract(off)
   const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
   const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
-  const double cL = __builtin_sqrt(g * pL / rL);
-  const double cR = __builtin_sqrt(g * pR / rR);
+  double cL, cR, eL, eR;  // the ideal-gas energies are not used (E is formed for side K below)
+  thermo_fp64<EOS>(rL, pL, g, cL, eL);
+  thermo_fp64<EOS>(rR, pR, g, cR, eR);
   double SL, SR;
   if constexpr (SPEEDS == SPEEDS_EINFELDT) {
     const double sL = __builtin_sqrt(rL), sR = __builtin_sqrt(rR);
@@ -200,7 +264,8 @@ __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], 
   const double r = useL ? rL : rR, u = useL ? uL : uR, v = useL ? vL : vR, w = useL ? wL : wR, p = useL ? pL : pR;
   const double SK = useL ? SL : SR;
   const bool star = useL ? !(0.0 <= SL) : (0.0 < SR);
-  const double E = p / (g - 1.0) + 0.5 * r * (u * u + v * v + w * w);
+  const double eK = (EOS == EOS_GAS_RADIATION) ? (useL ? eL : eR) : p / (g - 1.0);
+  const double E = eK + 0.5 * r * (u * u + v * v + w * w);
   const double FK[5] = {r * u, r * u * u + p, r * u * v, r * u * w, u * (E + p)};
   const double UK[5] = {r, r * u, r * v, r * w, E};
   const double a = r * (SK - u) / (SK - Ss);
@@ -307,15 +372,44 @@ __device__ __forceinline__ bool recover_fast(double U0, double U1, double U2, do
   return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
 }
 
-__device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t vs, double gm1, double W[5]) {
-  return recover(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gm1, W);
+// Recovery under either EOS (the gamma law is `recover`).  Gas + radiation:
+// p from the temperature of rho e = E - m.u/2; a state with rho e <= 0 has
+// no temperature and keeps p = rho e, which the check reports.
+template <int EOS>
+__device__ __forceinline__ bool recover_eos(double U0, double U1, double U2, double U3, double U4, double gamma,
+                                            double W[5]) {
+#pragma clang fp contract(off)
+  if constexpr (EOS == EOS_IDEAL) {
+    return recover(U0, U1, U2, U3, U4, gamma - 1.0, W);
+  } else {
+    const double u = U1 / U0, v = U2 / U0, w = U3 / U0;
+    const double rhoe = U4 - 0.5 * (U1 * u + U2 * v + U3 * w);
+    double p = rhoe;
+    if (rhoe > 0.0) {
+      const double T = gr_temperature_e(U0, rhoe, gamma);
+      p = U0 * T + ARAD * T * T * T * T / 3.0;
+    }
+    W[0] = U0;
+    W[1] = u;
+    W[2] = v;
+    W[3] = w;
+    W[4] = p;
+    const double s = fabs(u) + fabs(v) + fabs(w) + p + U0;
+    return (U0 > 0.0) && (p > 0.0) && (s < __builtin_huge_val());
+  }
+}
+
+template <int EOS>
+__device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t vs, double gamma, double W[5]) {
+  return recover_eos<EOS>(p[0], p[vs], p[2 * vs], p[3 * vs], p[4 * vs], gamma, W);
 }
 
 // CFL rate of one cell, sum over active directions of (|u_d| + c)/dx_d.
-template <int DIM>
+template <int DIM, int EOS = EOS_IDEAL>
 __device__ __forceinline__ double cell_rate(const double W[5], double gamma, double dx0, double dx1, double dx2) {
 #pragma clang fp contract(off)
-  const double c = __builtin_sqrt(gamma * W[4] / W[0]);
+  double c, e;
+  thermo_fp64<EOS>(W[0], W[4], gamma, c, e);
   double lam = 0.0;
   lam += (fabs(W[1]) + c) / dx0;
   lam += (fabs(W[2]) + c) / dx1;
@@ -452,7 +546,7 @@ __device__ __forceinline__ void tile_setup(TileCtx &C, const StageArgs &A, const
 // One work item: NSUB tiles of TX x TY cells (one tile per NT threads),
 // marched over z planes [z0, z1).
 // ------------------------------------------------------------------------
-template <int TX, int TY, int NSUB, int DIM, int STAGE, int SPEEDS, int RECON>
+template <int TX, int TY, int NSUB, int DIM, int STAGE, int SPEEDS, int RECON, int EOS>
 __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__restrict__ it, unsigned char *lds,
                                          int slot, double dt, double &lam, int &bad, int &badblk) {
   using T = double;
@@ -500,7 +594,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
   // check for a non-physical cell
   auto prims = [&](const double (&U)[5], T (&W)[5], bool own) {
     double Wd[5];
-    if (!recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd)) {
+    if (!recover_eos<EOS>(U[0], U[1], U[2], U[3], U[4], gamma, Wd)) {
       bad = 1;
       if (own) badblk = min(badblk, b);
     }
@@ -603,7 +697,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
         Rr[2] = isx ? wr[2] : wr[1];
       }
       T Fr[5];
-      hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
+      hllc_fp64<SPEEDS, EOS>(Lr, Rr, gamma, Fr);
       out[0] = Fr[0];
       out[ostride] = isx ? Fr[1] : Fr[2];
       out[2 * ostride] = isx ? Fr[2] : Fr[1];
@@ -634,11 +728,11 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
     }
     if (STAGE == 2) {  // CFL rate of the new state (FP64)
       double W[5];
-      if (!recover(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gm1, W)) {
+      if (!recover_eos<EOS>(Unew[0], Unew[1], Unew[2], Unew[3], Unew[4], gamma, W)) {
         bad = 1;
         badblk = min(badblk, b);
       } else {
-        lam = fmax(lam, cell_rate<DIM>(W, gamma, dx0, dx1, dx2));
+        lam = fmax(lam, cell_rate<DIM, EOS>(W, gamma, dx0, dx1, dx2));
       }
     }
   };
@@ -727,7 +821,7 @@ __device__ __forceinline__ void run_tile(const StageArgs &A, const WorkItem *__r
         }
       }
       T Fr[5];
-      hllc_fp64<SPEEDS>(Lr, Rr, gamma, Fr);
+      hllc_fp64<SPEEDS, EOS>(Lr, Rr, gamma, Fr);
       fz[0] = Fr[0];
       fz[1] = Fr[3];
       fz[2] = Fr[2];
@@ -1262,10 +1356,11 @@ constexpr size_t stage_lds_bytes() {
 // registers, two waves) is held to three waves too: a few spilled dwords,
 // measured 4 % faster; its stage 2, and both stages of kernels that also
 // carry the 8x8 tile, spill too much at three and keep two.
-template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON>
+template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON, int EOS>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
-    (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1)) ? 3 : 1)))
+    (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1 && EOS == EOS_IDEAL)) ? 3 : 1)))
 void k_stage(StageArgs A) {
+  static_assert(EOS == EOS_IDEAL || !MIXED, "the gas + radiation EOS runs on the FP64 tile only");
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
   if (A.reset_time && blockIdx.x == 0 && threadIdx.x == 0) {
     // plain path: this launch precedes the stage-2 launch that accumulates
@@ -1291,14 +1386,14 @@ void k_stage(StageArgs A) {
             if (__builtin_amdgcn_readfirstlane(it->block[s]) < 0) break;
             __syncthreads();  // LDS is reused by the next tile
           }
-          run_tile<16, 16, 1, DIM, STAGE, SPEEDS, RECON>(A, it, lds, s, dt, lam, bad, badblk);
+          run_tile<16, 16, 1, DIM, STAGE, SPEEDS, RECON, EOS>(A, it, lds, s, dt, lam, bad, badblk);
         }
       }
     } else if (KMASK & 2) {
       if constexpr (MIXED)
         run_tile_mixed<8, 4, DIM, STAGE, SPEEDS, RECON>(A, it, lds, 0, dt, lam, bad, badblk);
       else
-        run_tile<8, 8, 4, DIM, STAGE, SPEEDS, RECON>(A, it, lds, 0, dt, lam, bad, badblk);
+        run_tile<8, 8, 4, DIM, STAGE, SPEEDS, RECON, EOS>(A, it, lds, 0, dt, lam, bad, badblk);
     }
     __syncthreads();  // LDS is reused by the next item
   }
@@ -1312,11 +1407,10 @@ void k_stage(StageArgs A) {
 }
 
 // CFL rate of the interior cells of the work list (FP64).
-template <int DIM, int KMASK>
+template <int DIM, int KMASK, int EOS>
 __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
   double lam = 0.0;
   int bad = 0, badblk = INT_MAX;
-  const double gm1 = A.gamma - 1.0;
   const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
   for (int i = first; i < A.nitems; i += gridDim.x) {
     const WorkItem *it = A.items + i;
@@ -1336,12 +1430,12 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
       const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
       for (int z = za; z < zb; ++z) {
         double W[5];
-        if (!load_prim(p + z * plane, B.ncell, gm1, W)) {
+        if (!load_prim<EOS>(p + z * plane, B.ncell, A.gamma, W)) {
           bad = 1;
           badblk = min(badblk, b);
           continue;
         }
-        lam = fmax(lam, cell_rate<DIM>(W, A.gamma, B.dx[0], B.dx[1], B.dx[2]));
+        lam = fmax(lam, cell_rate<DIM, EOS>(W, A.gamma, B.dx[0], B.dx[1], B.dx[2]));
       }
     }
   }
@@ -1369,17 +1463,17 @@ __global__ void k_finalize(DevTime *t, double cfl, int init) {
 // ------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------
-template <int DIM, bool MIXED, int STAGE, int SPEEDS, int RECON>
+template <int DIM, bool MIXED, int STAGE, int SPEEDS, int RECON, int EOS = EOS_IDEAL>
 static hipError_t launch_ks(int kmask, int grid, hipStream_t s, const StageArgs &a) {
   switch (kmask) {
     case 1:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS, RECON>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
       break;
   }
   return hipGetLastError();
@@ -1409,10 +1503,17 @@ static hipError_t launch_k(int kmask, int speeds, int recon, int grid, hipStream
   }
 }
 
-hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int grid, hipStream_t s,
-                        const StageArgs &a) {
+hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int eos, int grid,
+                        hipStream_t s, const StageArgs &a) {
   if (grid <= 0) return hipSuccess;
   const int k = kmask, w = speeds, r = recon;
+  if (eos == EOS_GAS_RADIATION) {  // FP64, Davis bounds, primitive PLM only (checked by the caller)
+    if (mixed || w != SPEEDS_DAVIS || r != RECON_PRIMITIVE) return hipErrorInvalidValue;
+    constexpr int D = SPEEDS_DAVIS, P = RECON_PRIMITIVE, G = EOS_GAS_RADIATION;
+    if (ndim == 2)
+      return stage == 1 ? launch_ks<2, false, 1, D, P, G>(k, grid, s, a) : launch_ks<2, false, 2, D, P, G>(k, grid, s, a);
+    return stage == 1 ? launch_ks<3, false, 1, D, P, G>(k, grid, s, a) : launch_ks<3, false, 2, D, P, G>(k, grid, s, a);
+  }
   if (ndim == 2) {
     if (mixed)
       return stage == 1 ? launch_k<2, true, 1>(k, w, r, grid, s, a) : launch_k<2, true, 2>(k, w, r, grid, s, a);
@@ -1422,20 +1523,28 @@ hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, 
   return stage == 1 ? launch_k<3, false, 1>(k, w, r, grid, s, a) : launch_k<3, false, 2>(k, w, r, grid, s, a);
 }
 
-hipError_t launch_lambda(int ndim, int kmask, int grid, hipStream_t s, const StageArgs &a) {
-  if (grid <= 0) return hipSuccess;
-  const bool t16 = kmask & 1;
+template <int EOS>
+static void launch_lambda_e(int ndim, bool t16, int grid, hipStream_t s, const StageArgs &a) {
   if (ndim == 2) {
     if (t16)
-      hipLaunchKernelGGL((k_lambda<2, 3>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_lambda<2, 3, EOS>), dim3(grid), dim3(WG), 0, s, a);
     else
-      hipLaunchKernelGGL((k_lambda<2, 2>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_lambda<2, 2, EOS>), dim3(grid), dim3(WG), 0, s, a);
   } else {
     if (t16)
-      hipLaunchKernelGGL((k_lambda<3, 3>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_lambda<3, 3, EOS>), dim3(grid), dim3(WG), 0, s, a);
     else
-      hipLaunchKernelGGL((k_lambda<3, 2>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_lambda<3, 2, EOS>), dim3(grid), dim3(WG), 0, s, a);
   }
+}
+
+hipError_t launch_lambda(int ndim, int kmask, int eos, int grid, hipStream_t s, const StageArgs &a) {
+  if (grid <= 0) return hipSuccess;
+  const bool t16 = kmask & 1;
+  if (eos == EOS_GAS_RADIATION)
+    launch_lambda_e<EOS_GAS_RADIATION>(ndim, t16, grid, s, a);
+  else
+    launch_lambda_e<EOS_IDEAL>(ndim, t16, grid, s, a);
   return hipGetLastError();
 }
 

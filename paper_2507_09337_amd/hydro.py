@@ -27,6 +27,7 @@ EINFELDT = 0x100  # OR into a precision: HLLC with Einfeldt wave-speed bounds
 PVRS = 0x200  # OR into a precision: HLLC with pressure-based (PVRS) wave-speed bounds
 CONSERVED = 0x400  # OR into a precision: PLM on the conserved variables
 CHARACTERISTIC = 0x800  # OR into a precision: PLM on the characteristic variables
+GAS_RADIATION = 0x1000  # with FP64 only: the gas + radiation equation of state
 NBR, OUTFLOW, PERIODIC_SELF = 0, 1, 2
 _NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "ENOMEM", 4: "ENONPHYS", 5: "ESTATE"}
 

@@ -126,7 +126,7 @@ def test_host_stream_rejects_bad_packets_on_host(case):
     assert e.value.code == H.EINVAL
 
 
-@pytest.mark.parametrize("prec", [2, 0x1000, 0x300, 0x701, 0xC01, 0x101 | 0x2000, -1])
+@pytest.mark.parametrize("prec", [2, 0x1001, 0x1100, 0x1400, 0x300, 0x701, 0xC01, 0x101 | 0x2000, -1])
 def test_bad_precision_codes_rejected_on_host(prec):
     m = I.independent_blocks([8, 8], 3)
     with pytest.raises(H.HydroError) as e:
@@ -136,7 +136,8 @@ def test_bad_precision_codes_rejected_on_host(prec):
 
 @pytest.mark.parametrize("prec", [H.FP64 | H.EINFELDT, H.FP32_FP64 | H.EINFELDT, H.FP64 | H.PVRS,
                                   H.FP32_FP64 | H.PVRS, H.FP64 | H.CONSERVED, H.FP32_FP64 | H.CONSERVED | H.PVRS,
-                                  H.FP64 | H.CHARACTERISTIC, H.FP32_FP64 | H.CHARACTERISTIC | H.EINFELDT])
+                                  H.FP64 | H.CHARACTERISTIC, H.FP32_FP64 | H.CHARACTERISTIC | H.EINFELDT,
+                                  H.FP64 | H.GAS_RADIATION])
 def test_method_variants_pass_host_validation(prec):
     """A valid code with method-variant flags gets past every host check; with
     no GPU the first device call then fails loudly."""

@@ -1,7 +1,8 @@
 """GPU parity of the method variants -- HLLC wave-speed bounds
 (HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS) and PLM on conserved variables
 (HYDRO_RECON_CONSERVED, alone and with Einfeldt bounds) and on characteristic
-variables (HYDRO_RECON_CHARACTERISTIC, alone and with PVRS bounds) -- against the oracle
+variables (HYDRO_RECON_CHARACTERISTIC, alone and with PVRS bounds) and the gas +
+radiation equation of state (HYDRO_EOS_GAS_RADIATION, FP64 only) -- against the oracle
 run with the same options, through the C ABI: FP64 <= 1e-12 relative per cell
 (floored), mixed L1(rho) <= 1e-5 on smooth flow; uniform states bitwise;
 conservation on a periodic blast; the host-resident packet path with each
@@ -26,7 +27,13 @@ VARIANTS = {
     "conserved-einfeldt": (H.CONSERVED | H.EINFELDT, dict(speeds=O.EINFELDT, recon=O.CONSERVED)),
     "characteristic": (H.CHARACTERISTIC, dict(recon=O.CHARACTERISTIC)),
     "characteristic-pvrs": (H.CHARACTERISTIC | H.PVRS, dict(speeds=O.PVRS, recon=O.CHARACTERISTIC)),
+    "gas-radiation": (H.GAS_RADIATION, dict(eos=O.GAS_RADIATION)),
 }
+FP64_ONLY = {H.GAS_RADIATION}
+
+
+def precisions(flags):
+    return (H.FP64,) if flags in FP64_ONLY else (H.FP64, H.FP32_FP64)
 
 
 @pytest.fixture(params=sorted(VARIANTS), scope="module")
@@ -55,7 +62,7 @@ def test_smooth_fp64_and_mixed(variant, tile):
     EF, opts = variant
     P = I.smooth3d(nblk=(3, 3, 3), nsteps=15)
     R, dts, t_ref = oracle_run(P.mesh, P.U0, P.nsteps, P.cfl, P.gamma, opts)
-    for prec in (H.FP64, H.FP32_FP64):
+    for prec in precisions(EF):
         arena = to_dev(P.U0)
         mesh = H.Mesh(P.mesh, arena)
         b = H.Batch([H.Packet(mesh, ids, prec | EF) for ids in P.packets])
@@ -113,6 +120,8 @@ def test_blast_plain_path_conservation(variant):
 @pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
 def test_uniform_state_bitwise(variant, prec):
     EF, _ = variant
+    if prec not in precisions(EF):
+        pytest.skip("this variant runs in FP64 only")
     m = I.block_grid((2, 1, 2), (16, 8, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
     U0 = I.uniform_state(m, gamma=1.4)
     arena = to_dev(U0)
