@@ -78,6 +78,28 @@ def test_smooth_fp64_and_mixed(variant, tile):
         mesh.close()
 
 
+def test_2d_smooth_fp64_and_mixed(variant):
+    """The 2D kernels of the variant: self-periodic blocks of 16^2 and 32^2
+    (16x16 tiles and z-free faces), smooth random flow."""
+    EF, opts = variant
+    m = I.independent_blocks([16, 32, 16], 2)
+    U0 = I.random_smooth_state(m, 5, 1.4)
+    R, dts, t_ref = oracle_run(m, U0, 10, 0.4, 1.4, opts)
+    for prec in precisions(EF):
+        arena = to_dev(U0)
+        mesh = H.Mesh(m, arena)
+        b = H.Batch([H.Packet(mesh, range(m.nblocks), prec | EF)])
+        t = b.run(10, 0.4, 1.4)
+        U = to_host(arena)
+        if prec == H.FP64:
+            assert abs(t - t_ref) <= 1e-12 * t_ref
+            assert rel_err(m, U, R) <= 1e-12
+        else:
+            assert l1_rho(m, U, R) <= 1e-5
+        b.close()
+        mesh.close()
+
+
 def test_sod2d_packet_path_fp64(variant):
     EF, opts = variant
     P = I.sod2d()
