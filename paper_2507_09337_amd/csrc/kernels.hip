@@ -8,7 +8,8 @@
 // variants, on the conserved variables with the face states recovered
 // afterwards, or on the characteristic variables of the primitive system),
 // HLLC with Davis (or, as variants, Einfeldt or PVRS) wave speeds, SSP-RK2
-// combine, CFL rate sum_d (|u_d| + c)/dx_d.
+// combine, CFL rate sum_d (|u_d| + c)/dx_d; as a further variant of the FP64
+// tile, a gas + radiation EOS in place of the gamma law.
 //
 // Design for CDNA4 (wave64, 160 KiB LDS per CU, 8 XCDs):
 //   * One workgroup = 256 threads = one x-y tile of a block (16x16) or four
@@ -42,7 +43,7 @@
 namespace hyd {
 
 // ------------------------------------------------------------------------
-// Arithmetic of the two precisions.
+// FP32 arithmetic of the mixed tile (FP64 uses IEEE division and square root).
 // ------------------------------------------------------------------------
 template <typename T>
 struct Arith;
