@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hydro_oracle.c")
 PINS = ["tests/test_oracle_pointwise.py", "tests/test_oracle_scheme.py", "tests/test_oracle_einfeldt.py",
-        "tests/test_oracle_pvrs.py", "tests/test_oracle_recon.py", "tests/test_oracle_eos.py"]
+        "tests/test_oracle_pvrs.py", "tests/test_oracle_recon.py", "tests/test_oracle_eos.py",
+        "tests/test_oracle_bruteforce.py"]
 
 MUTANTS = {
     "hllc-left-star-uses-SR": ("F[v] = FL[v] + SL * (Us[v] - UL[v]);", "F[v] = FL[v] + SR * (Us[v] - UL[v]);"),
