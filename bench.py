@@ -131,9 +131,23 @@ def oracle_region_run(P, steps):
     el = time.perf_counter() - t0
     cells = m.total_cells
     cpu = {"value": cells * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-           "sample": f"{len(ids)} blocks ({cells} cells) around the centred {len(P.meta['subset'])}-block subset "
+           "host": host_cpu(), "sample": f"{len(ids)} blocks ({cells} cells) around the centred {len(P.meta['subset'])}-block subset "
                      f"of the same workload, {steps} steps, {el:.1f} s"}
     return ids, m, U, dts, cpu
+
+
+def host_cpu() -> str:
+    """The host CPU's model name and the logical CPUs this process may use."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} logical CPUs available"
 
 
 def subset_errors(P, ids, m, Uref, U_gpu_sub):
@@ -374,7 +388,7 @@ def main():
             k += 1
         el = time.perf_counter() - t0
         cpu = {"value": m.total_cells * k / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"first {len(ids)} blocks as their own mesh, {k} steps, {el:.1f} s"}
+               "host": host_cpu(), "sample": f"first {len(ids)} blocks as their own mesh, {k} steps, {el:.1f} s"}
     if cpu:
         log("cpu_baseline", json.dumps(cpu))
 
