@@ -100,6 +100,31 @@ def test_2d_smooth_fp64_and_mixed(variant):
         mesh.close()
 
 
+def test_ragged_blocks_partly_filled_items(variant):
+    """Blocks only the 8x8 tiling covers (24x40, three planes, outflow), so
+    some four-tile items carry empty slots, whose garbage LDS must neither
+    reach a result nor raise a non-physical flag."""
+    EF, opts = variant
+    m = I.block_grid((3, 1, 2), (24, 40, 3), (0, 0, 0), (1, 1, 1), "outflow", 3)
+    prims = I.grid_field(m, lambda x, y, z: (1 + 0.2 * np.sin(2 * np.pi * (x + y)), 0.3 * np.cos(2 * np.pi * y),
+                                             0.2 * np.sin(2 * np.pi * x), 0.1 + 0 * x, 1 + 0.3 * np.cos(2 * np.pi * z)))
+    U0 = I.conserved_arena(m, prims, 1.4)
+    R, dts, t_ref = oracle_run(m, U0, 6, 0.4, 1.4, opts)
+    for prec in precisions(EF):
+        arena = to_dev(U0)
+        mesh = H.Mesh(m, arena)
+        b = H.Batch([H.Packet(mesh, range(m.nblocks), prec | EF)])
+        t = b.run(6, 0.4, 1.4)
+        U = to_host(arena)
+        if prec == H.FP64:
+            assert abs(t - t_ref) <= 1e-12 * t_ref
+            assert rel_err(m, U, R) <= 1e-12
+        else:
+            assert l1_rho(m, U, R) <= 1e-5
+        b.close()
+        mesh.close()
+
+
 def test_sod2d_packet_path_fp64(variant):
     EF, opts = variant
     P = I.sod2d()
