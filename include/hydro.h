@@ -156,7 +156,8 @@ hydro_status hydro_mesh_destroy(hydro_mesh *m);
 
 /* Create a packet (Sec. 4.3 DataPacket: n blocks chosen at run time) over the
  * listed blocks of mesh m, advanced in the given hydro_precision (optionally
- * OR at most one HYDRO_SPEEDS_* and one HYDRO_RECON_* variant).  block_ids:
+ * OR at most one HYDRO_SPEEDS_* and one HYDRO_RECON_* variant; or exactly
+ * HYDRO_FP64 | HYDRO_EOS_GAS_RADIATION).  block_ids:
  * host array of nblocks distinct ids.  Builds the packet's device work list.
  * Errors: EINVAL (empty, duplicate or out-of-range id, bad precision), ENOMEM,
  * EDEVICE. */
@@ -190,7 +191,7 @@ hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, d
 hydro_status hydro_packet_destroy(hydro_packet *p);
 
 /* A batch of packets of one mesh (all packets must share the mesh and the
- * precision code, wave-speed variant included; a block may appear in at most
+ * precision code, method variants included; a block may appear in at most
  * one packet of the batch).  Builds the concatenated device work
  * list used by the persistent batched launches.  Errors: EINVAL, ENOMEM,
  * EDEVICE. */
