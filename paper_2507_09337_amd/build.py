@@ -7,7 +7,6 @@ from __future__ import annotations
 
 import os
 import subprocess
-import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)

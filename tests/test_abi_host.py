@@ -3,7 +3,6 @@ include/hydro.h declares, and rejects bad arguments on the host (before any
 device call) with HYDRO_EINVAL and a message."""
 import ctypes as C
 
-import numpy as np
 import pytest
 
 from paper_2507_09337_amd import hydro as H

@@ -8,7 +8,6 @@ the pin tests load through ``HYDRO_ORACLE_LIB`` in a child pytest process.
 import os
 import subprocess
 import sys
-import tempfile
 
 import pytest
 

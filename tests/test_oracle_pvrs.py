@@ -26,7 +26,6 @@ import pytest
 
 from oracle import exact_riemann as ER
 from oracle import oracle as O
-from paper_2507_09337_amd import inputs as I
 from test_oracle_einfeldt import check_hllc_exact_properties, check_scheme_invariants, random_pair, sod_l1
 
 P = O.PVRS
