@@ -214,6 +214,16 @@ hydro_status hydro_batch_advance_plain(hydro_batch *b, double dt, double gamma);
  * holds the state of the failing step), EDEVICE. */
 hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out);
 
+/* hydro_batch_run with the device time of every step: HIP events recorded on
+ * the mesh stream before the first replay and after each replay of the step
+ * graph; step_ms (host array of nsteps doubles, required) receives each
+ * step's time in milliseconds (stage 1, stage 2 and the dt update, and the
+ * gaps between them).  The events are created and destroyed by the call; the
+ * replays themselves are those of hydro_batch_run.  Synchronising.
+ * Errors: as hydro_batch_run; EINVAL for a null step_ms. */
+hydro_status hydro_batch_run_timed(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out,
+                                   double *step_ms);
+
 hydro_status hydro_batch_destroy(hydro_batch *b);
 
 /* Launch configuration of the batched path and its autotuner (Sec. 7 of the

@@ -702,7 +702,12 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   return HYDRO_OK;
 }
 
-hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out) {
+}  // extern "C"
+
+// nsteps graph replays; with step_ms, HIP events on the mesh stream around
+// every replay give each step's device time.
+static hydro_status batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out,
+                              double *step_ms) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
   if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
@@ -720,13 +725,40 @@ hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double 
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
-  for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(b->gexec, m->stream));
+  std::vector<hipEvent_t> ev(step_ms ? nsteps + 1 : 0, nullptr);
+  hydro_status st = HYDRO_OK;
+  for (auto &x : ev)
+    if (!st && hipEventCreate(&x) != hipSuccess) st = fail(HYDRO_EDEVICE, "event create");
+  if (!st && step_ms && hipEventRecord(ev[0], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
+  for (int s = 0; s < nsteps && !st; ++s) {
+    if (hipGraphLaunch(b->gexec, m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "graph launch");
+    if (!st && step_ms && hipEventRecord(ev[s + 1], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
+  }
   DevTime h;
-  hydro_status st = read_time(m, b->d_time, h);
+  if (!st) st = read_time(m, b->d_time, h);  // synchronises the mesh stream
+  for (int s = 0; s < nsteps && !st && step_ms; ++s) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) != hipSuccess) st = fail(HYDRO_EDEVICE, "event time");
+    step_ms[s] = ms;
+  }
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (st) return st;
   if (h.status) return nonphys(h);
   if (t_out) *t_out = h.t;
   return HYDRO_OK;
+}
+
+extern "C" {
+
+hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out) {
+  return batch_run(b, nsteps, cfl, gamma, t_out, nullptr);
+}
+
+hydro_status hydro_batch_run_timed(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out,
+                                   double *step_ms) {
+  if (!step_ms) return fail(HYDRO_EINVAL, "step_ms must be non-null");
+  return batch_run(b, nsteps, cfl, gamma, t_out, step_ms);
 }
 
 hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *ms_out) {

@@ -77,6 +77,7 @@ def lib():
             "hydro_batch_create": [C.POINTER(C.c_void_p), i32, pp],
             "hydro_batch_advance_plain": [vp, dbl, dbl],
             "hydro_batch_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
+            "hydro_batch_run_timed": [vp, i32, dbl, dbl, C.POINTER(C.c_double), C.POINTER(C.c_double)],
             "hydro_batch_destroy": [vp],
             "hydro_batch_set_tiling": [vp, i32, i32, i32],
             "hydro_batch_set_launch": [vp, i32, i32],
@@ -215,6 +216,14 @@ class Batch:
         t = C.c_double(0.0)
         _check(lib().hydro_batch_run(self.h, int(nsteps), float(cfl), float(gamma), C.byref(t)), "hydro_batch_run")
         return t.value
+
+    def run_timed(self, nsteps: int, cfl: float, gamma: float) -> tuple[float, list]:
+        """run() with HIP events around every graph replay: (t, per-step device ms)."""
+        t = C.c_double(0.0)
+        ms = (C.c_double * max(int(nsteps), 1))()
+        _check(lib().hydro_batch_run_timed(self.h, int(nsteps), float(cfl), float(gamma), C.byref(t), ms),
+               "hydro_batch_run_timed")
+        return t.value, list(ms)[: int(nsteps)]
 
     def time_kernels(self, nsteps: int, cfl: float, gamma: float) -> dict:
         """Eager launches with HIP events: mean stage-1 / stage-2 kernel ms and ms per step."""

@@ -230,6 +230,27 @@ def test_deterministic_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_timed_run_matches_run_and_reports_step_times():
+    """hydro_batch_run_timed replays the same graph as hydro_batch_run (same
+    state and time, bitwise) and returns one positive device time per step."""
+    P = I.smooth3d(nblk=(2, 2, 2), nsteps=5)
+    outs, times = [], []
+    for timed in (False, True):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), H.FP32_FP64)])
+        if timed:
+            t, ms = b.run_timed(P.nsteps, P.cfl, P.gamma)
+            assert len(ms) == P.nsteps and all(x > 0.0 for x in ms)
+        else:
+            t = b.run(P.nsteps, P.cfl, P.gamma)
+        outs.append(to_host(arena))
+        times.append(t)
+        b.close()
+        mesh.close()
+    assert np.array_equal(outs[0], outs[1]) and times[0] == times[1]
+
+
 # ---------------------------------------------------- host-resident packets
 def test_host_resident_packets_match_device_batch_and_oracle():
     """Packets kept in pinned host memory, streamed through device slots (copy
