@@ -240,8 +240,8 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  *               re-reading the z halo of each block;
  *   zchunk: z planes per work item (0 = the whole block; 3D only).
  * Without a setting a class uses 16x16 tiles (8x8 if its extents need them)
- * on whole blocks, in z-runs of two when the class has at least 96 x (number
- * of CUs) 16x16 tiles (the shorter work list then still gives 16 rounds of
+ * on whole blocks, in z-runs of two when the class has at least 12 x (number
+ * of CUs) 16x16 tiles (the shorter work list then still gives two rounds of
  * resident workgroups).  get_config reports the tiling in effect (2..4 for
  * z-runs, where the blocks' +z links allow them).
  * Per batch, grid = workgroups per stage launch (0 = one per work item; else a

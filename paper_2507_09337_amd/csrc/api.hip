@@ -175,10 +175,12 @@ DevBlock make_devblock(const hydro_block_desc *all, int b, int ndim) {
 
 // ---------------------------------------------------------------- work lists
 // Default z-run length of a class of whole 16x16-tiled 3D blocks with
-// `tiles` tiles: two when the halved work list still gives 16 or more rounds
-// of resident workgroups (three per CU), so it costs no tail; else one.
+// `tiles` tiles: two when the halved work list still gives two or more rounds
+// of resident workgroups (three per CU), else one.  Measured: runs of two win
+// from 2.7 rounds up (4096 and 32768 tiles of 16^3 blocks); below two rounds
+// the idle share of the last round outweighs the saved z halo.
 int default_run(const hydro_mesh *m, int64_t tiles) {
-  return (m->ndim == 3 && m->num_cu > 0 && tiles / 2 >= 16 * 3 * (int64_t)m->num_cu) ? 2 : 1;
+  return (m->ndim == 3 && m->num_cu > 0 && tiles / 2 >= 2 * 3 * (int64_t)m->num_cu) ? 2 : 1;
 }
 
 // Items in block order; 8x8 tiles are packed four to an item (tiles of equal
