@@ -252,8 +252,10 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_launch
  * rebuild or relaunch accordingly (EINVAL for a tile the class cannot use, or
  * a value out of range).  hydro_batch_autotune times every candidate tiling of
- * every class present (stage-1 launches on the class's own blocks; they write
- * only the mesh's scratch stage buffer, never the arena), rejects a candidate
+ * every class present (the median device time of a stage-1 and of a stage-2
+ * launch on the class's own blocks, summed; both write only the mesh's
+ * scratch stage buffer, never the arena: stage 2 is timed on the state
+ * itself), rejects a candidate
  * whose stage-1 result differs from the default tiling's by more than 1e-13
  * relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the fastest, then
  * picks grid and xcd_remap the same way.  reps = timed launches per candidate

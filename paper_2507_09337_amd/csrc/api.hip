@@ -1134,33 +1134,47 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
 }
 
 // Median time of `reps` stage-1 launches of a work list (ms).
-static hydro_status time_stage1(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
-                                double &ms) {
+// Device time (ms) of one RK step of work list wl: the median over `reps`
+// launches of each stage, summed.  Stage 1 reads the state and writes the U1
+// scratch, as in a step; stage 2 is timed on the state itself (source and Un
+// both the arena) and writes the U1 scratch too, so the caller's state is
+// never modified.  Both stages are timed because a tiling can shift work
+// between them (stage 2 carries Un and the CFL rate).
+static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
+                              double &ms) {
   hydro_mesh *m = b->m;
   const int prec = b->prec;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  std::vector<double> t;
   hydro_status st = HYDRO_OK;
-  const double dt = 1e-30;  // the result is scratch; any positive dt
-  StageArgs a = stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0, remap);
-  st = launch_stage_wl(m, prec, 1, wl, grid, m->stream, a);  // warm-up
-  for (int r = 0; r < reps && !st; ++r) {
-    (void)hipEventRecord(e0, m->stream);
-    st = launch_stage_wl(m, prec, 1, wl, grid, m->stream, a);
-    (void)hipEventRecord(e1, m->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
-    float f = 0;
-    (void)hipEventElapsedTime(&f, e0, e1);
-    t.push_back(f);
+  const double dt = 1e-30;  // the results are scratch; any positive dt
+  StageArgs args[2] = {stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0, remap),
+                       stage_args(m, wl, 2, dt, nullptr, b->d_time, gamma, 0, remap)};
+  args[1].src = m->arena;
+  args[1].dst = m->u1;
+  ms = 0.0;
+  for (int stage = 1; stage <= 2 && !st; ++stage) {
+    const StageArgs &a = args[stage - 1];
+    std::vector<double> t;
+    st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a);  // warm-up
+    for (int r = 0; r < reps && !st; ++r) {
+      (void)hipEventRecord(e0, m->stream);
+      st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a);
+      (void)hipEventRecord(e1, m->stream);
+      if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
+      float f = 0;
+      (void)hipEventElapsedTime(&f, e0, e1);
+      t.push_back(f);
+    }
+    if (!st) {
+      std::sort(t.begin(), t.end());
+      ms += t[t.size() / 2];
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
-  std::sort(t.begin(), t.end());
-  ms = t[t.size() / 2];
-  return HYDRO_OK;
+  return st;
 }
 
 static hydro_status stage1_sample(hydro_batch *b, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
@@ -1249,7 +1263,7 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
       st = upload_items(items, kmask, wl, m->stream);
       if (st) return st;
       double ms = 0;
-      st = time_stage1(b, wl, 0, b->remap, gamma, reps, ms);
+      st = time_step(b, wl, 0, b->remap, gamma, reps, ms);
       (void)hipFree(wl.d_items);
       if (st) return st;
       if (ms < best) {
@@ -1269,7 +1283,7 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
     for (int g : {0, 2 * m->num_cu, 4 * m->num_cu, 8 * m->num_cu}) {
       if (g > 0 && g >= b->wl.nitems) continue;
       double ms = 0;
-      st = time_stage1(b, b->wl, g, r, gamma, reps, ms);
+      st = time_step(b, b->wl, g, r, gamma, reps, ms);
       if (st) return st;
       if (ms < best) {
         best = ms;
