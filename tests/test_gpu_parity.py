@@ -230,6 +230,30 @@ def test_deterministic_bitwise():
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
+def test_autotune_leaves_the_state_untouched(prec):
+    """The tuner launches both RK stages of every candidate; they write only
+    the library's scratch buffer, so the caller's arena is bitwise unchanged
+    and a run afterwards equals a run without tuning."""
+    P = I.smooth3d(nblk=(2, 2, 4), nsteps=3)
+    outs = []
+    for tune in (False, True):
+        arena = to_dev(P.U0)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), prec)])
+        if tune:
+            b.autotune(P.gamma, reps=1)
+            assert np.array_equal(to_host(arena), P.U0)
+        b.run(P.nsteps, P.cfl, P.gamma)
+        outs.append(to_host(arena))
+        b.close()
+        mesh.close()
+    if prec == H.FP64:  # any tiling reproduces the oracle's rounding
+        assert np.array_equal(outs[0], outs[1])
+    else:
+        assert l1_rho(P.mesh, outs[1], outs[0]) <= 1e-6
+
+
 def test_timed_run_matches_run_and_reports_step_times():
     """hydro_batch_run_timed replays the same graph as hydro_batch_run (same
     state and time, bitwise) and returns one positive device time per step."""
