@@ -11,6 +11,21 @@ from paper_2507_09337_amd import inputs as I
 FAKE_ARENA = C.c_void_p(0x10000)  # never dereferenced: validation fails first
 
 
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++11")])
+def test_header_is_plain_c(lang, std):
+    """include/hydro.h needs no HIP or C++ header: it compiles on its own as
+    C99 and as C++ (plain pointers, sizes and opaque handles only)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no gcc")
+    r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-Werror", "-x", lang, std, H.HEADER], capture_output=True,
+                       text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_library_exports_every_declared_function():
     names = H.declared_functions()
     assert len(names) >= 15
