@@ -11,9 +11,14 @@
  *     DataPacket that carries everything the TaskFunction needs;
  *   - Sec. 4.3 (DataItem Generators): a DataPacket concatenates n AMR blocks,
  *     n chosen at run time, because single blocks are too small to use a GPU;
- *   - Sec. 4 (static-code requirements): the code is thread safe, never
- *     allocates scratch space itself (it is handed in), and keeps no
- *     non-constant globals;
+ *   - Sec. 4 (static-code requirements) asks generated code to be thread
+ *     safe, to take its scratch space from the caller and to keep no
+ *     non-constant globals.  This library departs from all three, for the
+ *     reasons given here: handles are not thread safe (below: the caller
+ *     serialises calls on one mesh, so no lock sits on the launch path); the
+ *     create calls allocate the device scratch of the stage buffer, block
+ *     table, work lists and time record once, and the step calls allocate
+ *     nothing; the error message is a thread-local global string;
  *   - Sec. 5.1 (Flash-X): blocks hold equal numbers of equally sized cells;
  *   - Sec. 5.2 (Sedov): ideal-gas gamma-law equation of state;
  *   - Sec. 6 (Experiments): explicit finite volume with a guard-cell halo,
@@ -139,6 +144,11 @@ typedef struct hydro_packet hydro_packet; /* an ordered list of blocks of one me
 typedef struct hydro_batch hydro_batch;   /* packets advanced stage-synchronously together      */
 
 /* Create a mesh over a caller-owned device arena of arena_len doubles.
+ * The mesh is the set of blocks the paper's solver works on (Sec. 5.1: the
+ * domain is cut into blocks of equally many equal cells) with, per block
+ * face, where its guard-cell halo comes from (Sec. 6: the halo around the
+ * block being updated; the paper fills it by MPI outside the task, here the
+ * kernels gather it from the linked neighbour's interior).
  * blocks: host array of nblocks descriptors (copied).  ndim: 2 or 3.
  * Block ranges [offset, offset + 5*ncell) must lie inside the arena and must
  * not overlap.  stream: hipStream_t used for all work on this mesh.
@@ -178,7 +188,12 @@ hydro_status hydro_packet_create(hydro_mesh *m, const int32_t *block_ids, int32_
 hydro_status hydro_packet_advance(hydro_packet *p, double dt, double gamma);
 
 /* dt = cfl / max over the packet's interior cells of sum_d (|u_d| + c)/dx_d,
- * c = sqrt(gamma p / rho), computed in FP64 on the device.  If the last call
+ * c = sqrt(gamma p / rho), computed in FP64 on the device.  The paper does
+ * not state its time-step rule; this is the CFL condition of an unsplit
+ * method-of-lines update (the rates of all directions summed), taken from
+ * the state at the start of a step and held for both RK stages.  A mesh-wide
+ * dt is the minimum of its packets' values (one dt per step for the whole
+ * mesh).  If the last call
  * on this packet was an advance with the same gamma, the rate it reduced is
  * used; otherwise the arena is read again.  (A caller that writes the arena
  * between an advance and this call must pass a different gamma or create a
@@ -192,26 +207,40 @@ hydro_status hydro_packet_destroy(hydro_packet *p);
 
 /* A batch of packets of one mesh (all packets must share the mesh and the
  * precision code, method variants included; a block may appear in at most
- * one packet of the batch).  Builds the concatenated device work
+ * one packet of the batch).  The paper sends packets to the GPU one by one
+ * (Sec. 4.3) and finds that many blocks are needed to fill the device
+ * (Sec. 6.1); a batch takes that to its end, all packets of a step in one
+ * launch per RK stage (the paper is silent on batching across packets).  Builds the concatenated device work
  * list used by the persistent batched launches.  Errors: EINVAL, ENOMEM,
  * EDEVICE. */
 hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, hydro_batch **out);
 
-/* One SSP-RK2 step of every packet with per-packet launches: stage 1 of every
- * packet, then stage 2 of every packet (stage-synchronous, so packets need
- * not be closed).  Each packet then holds its reduced CFL rate for
+/* One SSP-RK2 step of every packet with per-packet launches, the paper's
+ * packet-at-a-time offload (Sec. 4.3) with the guard refresh between the
+ * stages that Sec. 6 requires: stage 1 of every packet, then stage 2 of every
+ * packet (stage-synchronous, so packets need not be closed).  Each packet then holds its reduced CFL rate for
  * hydro_packet_reduce_dt.  Asynchronous.  Errors: EINVAL, EDEVICE. */
 hydro_status hydro_batch_advance_plain(hydro_batch *b, double dt, double gamma);
 
-/* nsteps SSP-RK2 steps of the whole batch with dt = cfl / max rate taken
- * from the state at the start of each step and kept on the device: one
+/* nsteps SSP-RK2 steps of the whole batch (Sec. 6: 2nd-order Runge-Kutta,
+ * guards refreshed before each stage -- here by the launch boundary between
+ * the stages) with dt = cfl / max rate (the rule of hydro_packet_reduce_dt)
+ * taken from the state at the start of each step and kept on the device: one
  * persistent launch per RK stage over the concatenated work list of all
  * packets, one captured HIP graph per step, replayed nsteps times with no
  * host synchronisation in between.  Synchronising.  *t_out (host, may be
  * NULL) receives the simulated time advanced.  The first call with a given
  * (cfl, gamma) instantiates the graph.
- * Errors: EINVAL, ENONPHYS (the state became non-physical; the arena then
- * holds the state of the failing step), EDEVICE. */
+ * Failure: when a step produces a state with rho <= 0, p <= 0 or a
+ * non-finite value (seen by the second stage, which recovers the first-stage
+ * state and reduces the CFL rate of the new one; a bad initial state is seen
+ * by the rate reduction before the first step), the device dt becomes NaN and
+ * every later stage launch of the run returns without touching the arena.  The
+ * call then returns ENONPHYS with the arena holding the result of the failing
+ * step (the initial state, unchanged, if that was bad) and *t_out the time at
+ * the end of that step.  Where the failure was a first-stage state, the cells
+ * whose stencil reached it hold non-finite values.
+ * Errors: EINVAL, ENONPHYS (as above), EDEVICE. */
 hydro_status hydro_batch_run(hydro_batch *b, int32_t nsteps, double cfl, double gamma, double *t_out);
 
 /* hydro_batch_run with the device time of every step: HIP events recorded on
@@ -254,11 +283,12 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * a value out of range).  hydro_batch_autotune times every candidate tiling of
  * every class present (the median device time of a stage-1 and of a stage-2
  * launch on the class's own blocks, summed; both write only the mesh's
- * scratch stage buffer, never the arena: stage 2 is timed on the state
- * itself), rejects a candidate
- * whose stage-1 result differs from the default tiling's by more than 1e-13
- * relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the fastest, then
- * picks grid and xcd_remap the same way.  reps = timed launches per candidate
+ * scratch stage buffer, never the arena: stage 2 takes its stencil from the
+ * arena and its pointwise Un from the scratch buffer, which it overwrites),
+ * rejects a candidate whose stage-1 or stage-2 result (stage 2 run with the
+ * arena as stencil and Un) differs from the default tiling's by more than
+ * 1e-13 relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the
+ * fastest, then picks grid and xcd_remap the same way.  reps = timed launches per candidate
  * (>= 1).  Synchronising.  hydro_batch_get_config writes grid to out[0],
  * xcd_remap to out[1], then (edge, tile, zchunk, ncells_in_class_low31) for
  * each class from out[2], up to nclass_max classes (out holds 2 + 4 *
@@ -310,9 +340,11 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
                                  int32_t precision, int32_t nslots, hydro_stream **out);
 
 /* nsteps steps of every packet, in place in the host arena.  Synchronising;
- * *t_out (may be NULL) receives the simulated time advanced.  Errors: EINVAL,
- * ENONPHYS (the arena then holds the failing step's results of the packets
- * already copied back), EDEVICE. */
+ * *t_out (may be NULL) receives the simulated time advanced.  A non-physical
+ * state is handled as in hydro_batch_run: the steps after the failing one
+ * copy every packet in and back unchanged, so the host arena holds the
+ * result of the failing step and *t_out its end time.  Errors: EINVAL,
+ * ENONPHYS, EDEVICE. */
 hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, double gamma, double *t_out);
 
 hydro_status hydro_stream_destroy(hydro_stream *s);

@@ -577,7 +577,7 @@ hydro_status hydro_packet_reduce_dt(hydro_packet *p, double gamma, double cfl, d
   if (!(p->lam_valid && p->lam_gamma == gamma)) {
     hipError_t e = hyd::launch_reset(p->d_time, m->stream);
     if (e == hipSuccess)
-      e = hyd::launch_lambda(m->ndim, p->wl.kmask, eos_of(p->prec), p->wl.nitems, m->stream,
+      e = hyd::launch_lambda(m->ndim, is_mixed(p->prec), p->wl.kmask, eos_of(p->prec), p->wl.nitems, m->stream,
                              stage_args(m, p->wl, 1, 0.0, nullptr, p->d_time, gamma, 0));
     if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("rate launch: ") + hipGetErrorString(e));
   }
@@ -723,7 +723,7 @@ static hydro_status batch_run(hydro_batch *b, int32_t nsteps, double cfl, double
   // dt of the first step from the current state
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
-    e = hyd::launch_lambda(m->ndim, b->wl.kmask, eos_of(b->prec), grid_of(b->wl, b->grid), m->stream,
+    e = hyd::launch_lambda(m->ndim, is_mixed(b->prec), b->wl.kmask, eos_of(b->prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
@@ -746,8 +746,10 @@ static hydro_status batch_run(hydro_batch *b, int32_t nsteps, double cfl, double
   for (auto &x : ev)
     if (x) (void)hipEventDestroy(x);
   if (st) return st;
-  if (h.status) return nonphys(h);
+  // after a failure t is the time at the end of the failing step (later
+  // replays left the state and t alone)
   if (t_out) *t_out = h.t;
+  if (h.status) return nonphys(h);
   return HYDRO_OK;
 }
 
@@ -773,7 +775,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   for (auto *p : b->packets) p->lam_valid = false;
   hipError_t e = hyd::launch_reset(b->d_time, m->stream);
   if (e == hipSuccess)
-    e = hyd::launch_lambda(m->ndim, b->wl.kmask, eos_of(prec), grid_of(b->wl, b->grid), m->stream,
+    e = hyd::launch_lambda(m->ndim, is_mixed(prec), b->wl.kmask, eos_of(prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
@@ -1015,7 +1017,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   for (int p = 0; p < np && good; ++p) {
     auto &sl = s->slots[s->pslot[p]];
     copy_in(p, sl);
-    good = good && ok(hyd::launch_lambda(s->ndim, s->wl[p].kmask, eos_of(prec), s->wl[p].nitems, sl.stream,
+    good = good && ok(hyd::launch_lambda(s->ndim, is_mixed(prec), s->wl[p].kmask, eos_of(prec), s->wl[p].nitems, sl.stream,
                                          slot_args(s, sl, s->wl[p], 1, gamma)));
     if (p == lastp[s->pslot[p]]) done(sl);
   }
@@ -1054,8 +1056,8 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
     for (auto &sl : s->slots) (void)hipStreamSynchronize(sl.stream);
     return fail(HYDRO_EDEVICE, std::string("stream run: ") + hipGetErrorString(hipGetLastError()));
   }
-  if (h.status) return nonphys(h);
   if (t_out) *t_out = h.t;
+  if (h.status) return nonphys(h);
   return HYDRO_OK;
 }
 
@@ -1133,13 +1135,15 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
   return HYDRO_OK;
 }
 
-// Median time of `reps` stage-1 launches of a work list (ms).
 // Device time (ms) of one RK step of work list wl: the median over `reps`
 // launches of each stage, summed.  Stage 1 reads the state and writes the U1
-// scratch, as in a step; stage 2 is timed on the state itself (source and Un
-// both the arena) and writes the U1 scratch too, so the caller's state is
-// never modified.  Both stages are timed because a tiling can shift work
-// between them (stage 2 carries Un and the CFL rate).
+// scratch, as in a step.  Stage 2 takes its stencil from the state and its
+// pointwise Un from the U1 scratch, and writes the U1 scratch (each thread
+// reads Un only at its own cells before it writes them), so it moves the
+// bytes of a real stage 2 -- a stencil source and a separate pointwise
+// buffer -- while the caller's state is never modified.  Both stages are
+// timed because a tiling can shift work between them (stage 2 carries Un
+// and the CFL rate).
 static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
                               double &ms) {
   hydro_mesh *m = b->m;
@@ -1152,6 +1156,7 @@ static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int 
   StageArgs args[2] = {stage_args(m, wl, 1, dt, nullptr, b->d_time, gamma, 0, remap),
                        stage_args(m, wl, 2, dt, nullptr, b->d_time, gamma, 0, remap)};
   args[1].src = m->arena;
+  args[1].un = m->u1;
   args[1].dst = m->u1;
   ms = 0.0;
   for (int stage = 1; stage <= 2 && !st; ++stage) {
@@ -1177,8 +1182,14 @@ static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int 
   return st;
 }
 
-static hydro_status stage1_sample(hydro_batch *b, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
-                                  double gamma, std::vector<double> &out) {
+// Results of the listed blocks after one launch of the given stage with
+// tiling `cfg`, written to the U1 scratch and read back: stage 1 from the
+// state; stage 2 with the state as both its stencil source and its pointwise
+// Un (a valid stage-2 input whose every neighbour value is defined, so the
+// stage-2 code path -- z-run marching, the Un stream, the rate epilogue -- is
+// compared on the sample alone).
+static hydro_status stage_sample(hydro_batch *b, int stage, const std::vector<int32_t> &ids,
+                                 const std::map<int, TileCfg> &cfg, double gamma, std::vector<double> &out) {
   hydro_mesh *m = b->m;
   std::vector<WorkItem> items;
   int kmask;
@@ -1186,8 +1197,11 @@ static hydro_status stage1_sample(hydro_batch *b, const std::vector<int32_t> &id
   build_items(m, ids, cfg, items, kmask);
   hydro_status st = upload_items(items, kmask, wl, m->stream);
   if (st) return st;
-  st = launch_stage_wl(m, b->prec, 1, wl, 0, m->stream,
-                       stage_args(m, wl, 1, 1e-3, nullptr, b->d_time, gamma, 0));
+  StageArgs a = stage_args(m, wl, stage, 1e-3, nullptr, b->d_time, gamma, 0);
+  a.src = m->arena;
+  a.un = m->arena;
+  a.dst = m->u1;
+  st = launch_stage_wl(m, b->prec, stage, wl, 0, m->stream, a);
   out.clear();
   for (int id : ids) {
     if (st) break;
@@ -1238,23 +1252,28 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
         c.tile = k;
         cands.push_back(c);
       }
-    // parity reference: default tiling on a sample of blocks
+    // parity reference: default tiling on a sample of blocks, both stages
     std::vector<int32_t> sample(ids.begin(), ids.begin() + std::min<size_t>(ids.size(), 64));
-    std::vector<double> ref, got;
-    hydro_status st = stage1_sample(b, sample, {}, gamma, ref);
+    std::vector<double> ref[2], got;
+    hydro_status st = HYDRO_OK;
+    for (int stage = 1; stage <= 2 && !st; ++stage) st = stage_sample(b, stage, sample, {}, gamma, ref[stage - 1]);
     if (st) return st;
     double best = 1e300;
     TileCfg bestc;
     for (const TileCfg &c : cands) {
       std::map<int, TileCfg> one;
       one[edge] = c;
-      st = stage1_sample(b, sample, one, gamma, got);
-      if (st) return st;
-      bool ok = got.size() == ref.size();
-      double scale = 0.0;
-      for (double r : ref) scale = std::max(scale, std::fabs(r));
-      for (size_t i = 0; ok && i < ref.size(); ++i)
-        ok = std::fabs(got[i] - ref[i]) <= tol * (std::fabs(ref[i]) + 1e-6 * scale);
+      bool ok = true;
+      for (int stage = 1; stage <= 2 && ok; ++stage) {
+        st = stage_sample(b, stage, sample, one, gamma, got);
+        if (st) return st;
+        const std::vector<double> &r = ref[stage - 1];
+        ok = got.size() == r.size();
+        double scale = 0.0;
+        for (double x : r) scale = std::max(scale, std::fabs(x));
+        for (size_t i = 0; ok && i < r.size(); ++i)
+          ok = std::fabs(got[i] - r[i]) <= tol * (std::fabs(r[i]) + 1e-6 * scale);
+      }
       if (!ok) continue;
       std::vector<WorkItem> items;
       int kmask;

@@ -72,7 +72,9 @@ struct StageArgs {
 // eos: 0 = gamma law, 1 = gas + radiation (FP64 with Davis bounds and primitive PLM only).
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int eos, int grid,
                         hipStream_t s, const StageArgs &a);
-hipError_t launch_lambda(int ndim, int kmask, int eos, int grid, hipStream_t s, const StageArgs &a);
+// mixed: the rate as the mixed path's stage 2 reduces it (refined hardware
+// reciprocal and reciprocal square root); else in oracle order.
+hipError_t launch_lambda(int ndim, bool mixed, int kmask, int eos, int grid, hipStream_t s, const StageArgs &a);
 hipError_t launch_reset(DevTime *t, hipStream_t s);
 hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s);
 

@@ -98,6 +98,20 @@ def lib():
     return _lib
 
 
+_lib_hash = None
+
+
+def library_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the library file."""
+    global _lib_hash
+    if _lib_hash is None:
+        import hashlib
+
+        with open(LIB_PATH, "rb") as f:
+            _lib_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _lib_hash
+
+
 def _check(rc: int, what: str):
     if rc != OK:
         raise HydroError(rc, what, lib().hydro_last_error().decode())
@@ -264,7 +278,10 @@ class Batch:
         return cfg
 
     def tuning_key(self) -> str:
-        """Device | precision code | ndim | (class edge: cells, ...) of this batch."""
+        """Library build | device | precision code | ndim | (class edge: cells,
+        ...) of this batch.  The build is a hash of the loaded library file, so
+        an entry stored by another build of the kernels is never applied
+        without its parity check."""
         try:
             import torch
 
@@ -272,7 +289,7 @@ class Batch:
         except Exception:
             dev = "gpu"
         classes = ",".join(f"{c['edge']}:{c['cells']}" for c in self.config()["classes"])
-        return f"{dev}|prec={self.packets[0].precision}|ndim={self.packets[0].mesh.ndim}|{classes}"
+        return f"lib={library_hash()}|{dev}|prec={self.packets[0].precision}|ndim={self.packets[0].mesh.ndim}|{classes}"
 
     def apply_config(self, cfg: dict):
         """Apply a configuration as returned by config() / autotune()."""

@@ -200,6 +200,119 @@ def test_nonphysical_state_reported():
     assert e.value.code == H.ENONPHYS
 
 
+def test_bad_initial_state_leaves_the_arena_untouched():
+    """A non-physical initial state is caught by the rate reduction before the
+    first step: every stage launch of the run then returns at once, so the
+    arena (and, through staging slots, the host arena) is bitwise unchanged."""
+    import torch
+
+    m = I.block_grid((2, 1, 1), (16, 16, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    U0 = I.uniform_state(m, gamma=1.4)
+    m.block_view(U0, 1)[4, 3, 5, 7] = 0.0  # E < rho|v|^2/2
+    for prec in (H.FP64, H.FP32_FP64):
+        arena = to_dev(U0)
+        mesh = H.Mesh(m, arena)
+        b = H.Batch([H.Packet(mesh, range(m.nblocks), prec)])
+        with pytest.raises(H.HydroError) as e:
+            b.run(5, 0.4, 1.4)
+        assert e.value.code == H.ENONPHYS and "block 1" in str(e.value)
+        assert np.array_equal(to_host(arena), U0)
+        mesh.close()
+        host = torch.from_numpy(U0.copy()).pin_memory()
+        hs = H.HostStream(m, host, [[0, 1]], prec, 2)
+        with pytest.raises(H.HydroError) as e:
+            hs.run(5, 0.4, 1.4)
+        assert e.value.code == H.ENONPHYS
+        hs.close()
+        assert np.array_equal(host.numpy(), U0)
+
+
+def _unstable_sod():
+    """2D Sod at CFL 2.3, far above the scheme's stable limit: the growing
+    instability makes a pressure negative.  The oracle's state after the
+    failing step is finite and non-physical (its next rate reduction
+    reports it)."""
+    P = I.sod2d()
+    cfl = 2.3
+    R = P.U0.copy()
+    t = 0.0
+    for k in range(40):
+        try:
+            dt = O.dt(P.mesh, R, P.gamma, cfl)
+        except O.OracleError as e:
+            assert e.code == O.ENONPHYS
+            return P, cfl, R, k, t
+        O.step(P.mesh, R, dt, P.gamma)
+        t += dt
+    raise AssertionError("the unstable run did not fail")
+
+
+def test_failing_step_result_kept_fp64():
+    """Graph path and host-resident packets: a run of 20 steps whose k-th step
+    makes the state non-physical returns ENONPHYS with the arena holding the
+    result of step k (equal to the oracle's state after k steps, finite) and
+    t the time at its end; the replays after it touch nothing."""
+    import torch
+
+    P, cfl, R, k, t_ref = _unstable_sod()
+    assert 2 <= k < 20 and np.isfinite(R).all()
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), H.FP64)])
+    t = C_double_run(b, 20, cfl, P.gamma)
+    U = to_host(arena)
+    assert np.isfinite(U).all()
+    assert rel_err(P.mesh, U, R) <= TOL64
+    assert abs(t - t_ref) <= TOL64 * t_ref
+    mesh.close()
+    host = torch.from_numpy(P.U0.copy()).pin_memory()
+    hs = H.HostStream(P.mesh, host, [list(range(P.mesh.nblocks))], H.FP64, 2)
+    with pytest.raises(H.HydroError) as e:
+        hs.run(20, cfl, P.gamma)
+    assert e.value.code == H.ENONPHYS
+    hs.close()
+    assert rel_err(P.mesh, host.numpy(), R) <= TOL64
+
+
+def C_double_run(b, nsteps, cfl, gamma):
+    """hydro_batch_run expected to fail with ENONPHYS; returns the t it reports."""
+    import ctypes as C
+
+    t = C.c_double(-1.0)
+    rc = H.lib().hydro_batch_run(b.h, int(nsteps), float(cfl), float(gamma), C.byref(t))
+    assert rc == H.ENONPHYS, rc
+    return t.value
+
+
+def test_failing_step_result_kept_mixed():
+    """The mixed path fails at its own step j of the unstable run (the first
+    run length n for which a run from the initial state reports ENONPHYS):
+    a run of 20 steps leaves bitwise the state and time of the run of j
+    steps, i.e. the steps after the failing one touch nothing."""
+    P, cfl, _, _, _ = _unstable_sod()
+    arena = to_dev(P.U0)
+    mesh = H.Mesh(P.mesh, arena)
+    b = H.Batch([H.Packet(mesh, range(P.mesh.nblocks), H.FP32_FP64)])
+    j = None
+    for n in range(1, 20):
+        arena.copy_(to_dev(P.U0))
+        try:
+            b.run(n, cfl, P.gamma)
+        except H.HydroError as e:
+            assert e.code == H.ENONPHYS
+            j = n
+            break
+    assert j is not None and j >= 2
+    U_j = to_host(arena)
+    arena.copy_(to_dev(P.U0))
+    t_j = C_double_run(b, j, cfl, P.gamma)
+    assert np.array_equal(to_host(arena), U_j)
+    arena.copy_(to_dev(P.U0))
+    t_20 = C_double_run(b, 20, cfl, P.gamma)
+    assert np.array_equal(to_host(arena), U_j) and t_20 == t_j
+    mesh.close()
+
+
 def test_open_packet_refuses_advance_and_batch_is_stage_synchronous():
     m = I.block_grid((2, 1, 1), (16, 16, 8), (0, 0, 0), (1, 1, 1), "periodic", 3)
     U0 = I.random_smooth_state(m, 3, 1.4)
