@@ -438,3 +438,29 @@ def test_autotune_results_cached_as_json(tmp_path):
         mesh.close()
     assert outs[0][0] == outs[1][0]
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
+def test_checkpoint_resume_bitwise(prec, tmp_path):
+    """20 steps in one run equal 10 steps, a save of the arena to a file, a new
+    mesh and batch over the loaded state, and 10 more steps -- bit for bit:
+    the run keeps no state but the arena and the time (the resumed run's
+    first dt is a fresh reduction, the same rate its stage 2 reduces)."""
+    P = I.smooth3d(nblk=(2, 2, 2), nsteps=20)
+
+    def run(U, n):
+        arena = to_dev(U)
+        mesh = H.Mesh(P.mesh, arena)
+        b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+        t = b.run(n, P.cfl, P.gamma)
+        out = to_host(arena)
+        mesh.close()
+        return out, t
+
+    U20, t20 = run(P.U0, 20)
+    U10, t10 = run(P.U0, 10)
+    path = tmp_path / "state.npy"
+    np.save(path, U10)
+    Ur, tr = run(np.load(path), 10)
+    assert np.array_equal(Ur, U20)
+    assert abs((t10 + tr) - t20) <= 1e-15 * t20
