@@ -349,6 +349,35 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
 
 hydro_status hydro_stream_destroy(hydro_stream *s);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free step, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  One full SSP-RK2 step of all nblocks blocks with time step dt,
+ * in place on the caller's device arena -- what hydro_packet_advance does for
+ * a packet of every block of a mesh made from the same descriptors -- but
+ * with no mesh, packet or other allocation: the first-stage state, the device
+ * block table, the work list and the time record live in one fixed array of
+ * the library, 64 MiB per GPU, held from the first call on that GPU until the
+ * process ends.
+ *   Limits: nblocks <= 4096, and 8 * arena_len + 176 * nblocks + 40 * (work
+ *   items) plus alignment must fit in 64 MiB (arena_len up to about 8.3e6
+ *   doubles, i.e. 1.6e6 cells); a larger mesh is EINVAL, checked before any
+ *   device work.
+ *   Tiling: 16x16 tiles where a block's x and y extents allow, else 8x8 tiles
+ *   packed four to a work item within the block; no z-runs, no tuning.
+ *   blocks: host array, read during the call (each block's resolved table
+ *   entry is passed to a setup kernel by value, so nothing refers to it
+ *   afterwards).  precision: as for hydro_packet_create.  stream: hipStream_t
+ *   of all the call's work (NULL = default stream); stream-ordered,
+ *   asynchronous.  The array keeps the last call's contents; every call
+ *   rewrites what it reads.  All calls on one GPU share the array, so calls
+ *   that overlap on one GPU (other streams, other threads) race: the caller
+ *   serialises them.
+ * Errors: EINVAL (descriptors as for hydro_mesh_create, precision, dt or gamma
+ * as for hydro_packet_advance, size beyond the limits), EDEVICE. */
+hydro_status hydro_step_static(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *arena,
+                               int64_t arena_len, int32_t precision, double dt, double gamma, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *hydro_last_error(void);
 

@@ -8,7 +8,10 @@
 #include <array>
 #include <chrono>
 #include <climits>
+#include <atomic>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -26,12 +29,20 @@ using hyd::WorkItem;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failing call on this thread: a fixed buffer, so that
+// reporting an error never allocates.
+thread_local char g_err[512];
 
-hydro_status fail(hydro_status s, const std::string &msg) {
-  g_err = msg;
+hydro_status failf(hydro_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+hydro_status failf(hydro_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
   return s;
 }
+
+hydro_status fail(hydro_status s, const std::string &msg) { return failf(s, "%s", msg.c_str()); }
 
 #define HIP_TRY(call)                                                                                 \
   do {                                                                                                \
@@ -108,46 +119,65 @@ struct hydro_batch {
 namespace {
 
 // ---------------------------------------------------------------- validation
+// Checks of one block descriptor (everything but overlap with other blocks):
+// nullptr if it is valid, else a message; *face receives the face concerned
+// (-1 if none).
+const char *block_error(const hydro_block_desc *blocks, int32_t nb, int32_t ndim, int64_t arena_len, int b,
+                        int *face) {
+  const hydro_block_desc &d = blocks[b];
+  *face = -1;
+  if (d.reserved != 0) return "reserved field must be 0";
+  if (d.n[0] < 8 || d.n[1] < 8 || d.n[0] % 8 || d.n[1] % 8) return "n[0] and n[1] must be positive multiples of 8";
+  if (d.n[0] > 16384 || d.n[1] > 16384) return "n[0], n[1] must be <= 16384";
+  if (ndim == 2 && d.n[2] != 1) return "n[2] must be 1 in 2D";
+  if (ndim == 3 && (d.n[2] < 2 || d.n[2] > 16384)) return "n[2] must be in [2, 16384] in 3D";
+  const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  if (nc >= ((int64_t)1 << 31)) return "too many cells";
+  for (int a = 0; a < ndim; ++a)
+    if (!finite_pos(d.dx[a])) return "dx must be finite and > 0";
+  if (d.offset < 0 || d.offset > arena_len - 5 * nc) return "range outside the arena";
+  for (int f = 0; f < 2 * ndim; ++f) {
+    *face = f;
+    const int k = d.face_kind[f];
+    if (k != HYDRO_NBR && k != HYDRO_OUTFLOW && k != HYDRO_PERIODIC_SELF) return "bad face kind";
+    if (k != HYDRO_NBR) continue;
+    const int s = d.nbr[f];
+    if (s < 0 || s >= nb) return "neighbour id out of range";
+    const int axis = f / 2;
+    for (int a = 0; a < 3; ++a)
+      if (a != axis && blocks[s].n[a] != d.n[a]) return "neighbour has other tangential extents";
+    if (blocks[s].n[axis] < 2) return "neighbour too thin for two guard layers";
+  }
+  *face = -1;
+  return nullptr;
+}
+
+// Descriptor checks of a mesh; `ranges` (nb entries of scratch, owned by the
+// caller) is sorted to find overlapping blocks.
+hydro_status validate_blocks(const hydro_block_desc *blocks, int32_t nb, int32_t ndim, const double *arena,
+                             int64_t arena_len, std::pair<int64_t, int64_t> *ranges) {
+  if (nb <= 0 || !blocks) return failf(HYDRO_EINVAL, "mesh: nblocks must be > 0 and blocks non-null");
+  if (ndim != 2 && ndim != 3) return failf(HYDRO_EINVAL, "mesh: ndim must be 2 or 3");
+  if (!arena || arena_len <= 0) return failf(HYDRO_EINVAL, "mesh: arena must be non-null with arena_len > 0");
+  for (int b = 0; b < nb; ++b) {
+    int face = -1;
+    if (const char *why = block_error(blocks, nb, ndim, arena_len, b, &face)) {
+      if (face >= 0) return failf(HYDRO_EINVAL, "mesh: block %d: %s on face %d", b, why, face);
+      return failf(HYDRO_EINVAL, "mesh: block %d: %s", b, why);
+    }
+    const hydro_block_desc &d = blocks[b];
+    ranges[b] = {d.offset, d.offset + 5 * (int64_t)d.n[0] * d.n[1] * d.n[2]};
+  }
+  std::sort(ranges, ranges + nb);
+  for (int i = 1; i < nb; ++i)
+    if (ranges[i].first < ranges[i - 1].second) return failf(HYDRO_EINVAL, "mesh: block ranges overlap in the arena");
+  return HYDRO_OK;
+}
+
 hydro_status validate_mesh(const hydro_block_desc *blocks, int32_t nb, int32_t ndim, const double *arena,
                            int64_t arena_len) {
-  if (nb <= 0 || !blocks) return fail(HYDRO_EINVAL, "mesh: nblocks must be > 0 and blocks non-null");
-  if (ndim != 2 && ndim != 3) return fail(HYDRO_EINVAL, "mesh: ndim must be 2 or 3");
-  if (!arena || arena_len <= 0) return fail(HYDRO_EINVAL, "mesh: arena must be non-null with arena_len > 0");
-  std::vector<std::pair<int64_t, int64_t>> ranges;
-  ranges.reserve(nb);
-  for (int b = 0; b < nb; ++b) {
-    const hydro_block_desc &d = blocks[b];
-    const std::string who = "mesh: block " + std::to_string(b) + ": ";
-    if (d.reserved != 0) return fail(HYDRO_EINVAL, who + "reserved field must be 0");
-    if (d.n[0] < 8 || d.n[1] < 8 || d.n[0] % 8 || d.n[1] % 8)
-      return fail(HYDRO_EINVAL, who + "n[0] and n[1] must be positive multiples of 8");
-    if (d.n[0] > 16384 || d.n[1] > 16384) return fail(HYDRO_EINVAL, who + "n[0], n[1] must be <= 16384");
-    if (ndim == 2 && d.n[2] != 1) return fail(HYDRO_EINVAL, who + "n[2] must be 1 in 2D");
-    if (ndim == 3 && (d.n[2] < 2 || d.n[2] > 16384)) return fail(HYDRO_EINVAL, who + "n[2] must be in [2, 16384] in 3D");
-    const int64_t nc = (int64_t)d.n[0] * d.n[1] * d.n[2];
-    if (nc >= ((int64_t)1 << 31)) return fail(HYDRO_EINVAL, who + "too many cells");
-    for (int a = 0; a < ndim; ++a)
-      if (!finite_pos(d.dx[a])) return fail(HYDRO_EINVAL, who + "dx must be finite and > 0");
-    if (d.offset < 0 || d.offset > arena_len - 5 * nc) return fail(HYDRO_EINVAL, who + "range outside the arena");
-    ranges.emplace_back(d.offset, d.offset + 5 * nc);
-    for (int f = 0; f < 2 * ndim; ++f) {
-      const int k = d.face_kind[f];
-      if (k != HYDRO_NBR && k != HYDRO_OUTFLOW && k != HYDRO_PERIODIC_SELF)
-        return fail(HYDRO_EINVAL, who + "bad face kind on face " + std::to_string(f));
-      if (k != HYDRO_NBR) continue;
-      const int s = d.nbr[f];
-      if (s < 0 || s >= nb) return fail(HYDRO_EINVAL, who + "neighbour id out of range on face " + std::to_string(f));
-      const int axis = f / 2;
-      for (int a = 0; a < 3; ++a)
-        if (a != axis && blocks[s].n[a] != d.n[a])
-          return fail(HYDRO_EINVAL, who + "neighbour on face " + std::to_string(f) + " has other tangential extents");
-      if (blocks[s].n[axis] < 2) return fail(HYDRO_EINVAL, who + "neighbour too thin for two guard layers");
-    }
-  }
-  std::sort(ranges.begin(), ranges.end());
-  for (size_t i = 1; i < ranges.size(); ++i)
-    if (ranges[i].first < ranges[i - 1].second) return fail(HYDRO_EINVAL, "mesh: block ranges overlap in the arena");
-  return HYDRO_OK;
+  std::vector<std::pair<int64_t, int64_t>> ranges(nb > 0 ? nb : 0);
+  return validate_blocks(blocks, nb, ndim, arena, arena_len, ranges.data());
 }
 
 DevBlock make_devblock(const hydro_block_desc *all, int b, int ndim) {
@@ -448,7 +478,7 @@ hydro_status rebuild_batch_items(hydro_batch *b) {
 // =================================================================== ABI
 extern "C" {
 
-const char *hydro_last_error(void) { return g_err.c_str(); }
+const char *hydro_last_error(void) { return g_err; }
 
 hydro_status hydro_mesh_create(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *arena,
                                int64_t arena_len, void *stream, hydro_mesh **out) {
@@ -1311,6 +1341,172 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
       }
     }
   return hydro_batch_set_launch(b, bestg, bestr);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- allocation-free step
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;  // per GPU
+constexpr int kStaticMaxBlocks = 4096;
+constexpr int kSetupChunk = 16;  // blocks per setup launch (kernel arguments <= 4 KiB)
+constexpr int kMaxDevices = 64;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Tiling of a block in the allocation-free step: 16x16 tiles where both
+// extents allow, else 8x8 tiles packed four to a work item within the block.
+int static_items_of(const hydro_block_desc &d, bool *t16) {
+  *t16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
+  const int T = *t16 ? 16 : 8;
+  const int tiles = (d.n[0] / T) * (d.n[1] / T);
+  return *t16 ? tiles : (tiles + 3) / 4;
+}
+
+// Up to kSetupChunk blocks' resolved table entries, passed to the setup
+// kernel by value, so that the host keeps no buffer alive after the launch.
+struct SetupChunk {
+  DevBlock blk[kSetupChunk];
+  int32_t id[kSetupChunk];     // block id of entry g
+  int32_t item0[kSetupChunk];  // first work item of block id[g]
+  int32_t count;
+};
+static_assert(sizeof(SetupChunk) <= 4096, "setup kernel arguments must stay within 4 KiB");
+static_assert(sizeof(DevBlock) == 176 && sizeof(WorkItem) == 40, "the static step's size limit in hydro.h counts these sizes");
+
+std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+}  // namespace
+
+// The fixed device scratch of hydro_step_static: the time record, the block
+// table, the work list and the first-stage state of one call.  Each GPU holds
+// its own copy from the library's first use there until the process ends.
+// Host code never passes this name to a kernel: it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// One workgroup per block of the chunk: the table entry, then the block's
+// work items (one per 16x16 tile, or one per four 8x8 tiles of the block with
+// empty slots marked -1), whole z range.
+__global__ void k_static_setup(SetupChunk c, DevBlock *table, WorkItem *items) {
+  const int g = blockIdx.x;
+  if (g >= c.count) return;
+  const DevBlock &B = c.blk[g];
+  const int id = c.id[g];
+  if (threadIdx.x == 0) table[id] = B;
+  const bool t16 = (B.n[0] % 16 == 0) && (B.n[1] % 16 == 0);
+  const int T = t16 ? 16 : 8;
+  const int tx = B.n[0] / T, ntile = tx * (B.n[1] / T);
+  const int nitem = t16 ? ntile : (ntile + 3) / 4;
+  for (int j = threadIdx.x; j < nitem; j += blockDim.x) {
+    WorkItem it;
+    it.kind = t16 ? hyd::KIND_T16 : hyd::KIND_T8;
+    it.z0 = 0;
+    it.z1 = (int16_t)B.n[2];
+    for (int s = 0; s < 4; ++s) {
+      const int t = t16 ? (s == 0 ? j : -1) : 4 * j + s;
+      const bool on = t >= 0 && t < ntile;
+      it.block[s] = on ? id : -1;
+      it.x0[s] = (int16_t)(on ? (t % tx) * T : 0);
+      it.y0[s] = (int16_t)(on ? (t / tx) * T : 0);
+    }
+    items[c.item0[g] + j] = it;
+  }
+}
+
+#define HIP_TRYF(call)                                                                                \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess) return failf(HYDRO_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+extern "C" {
+
+hydro_status hydro_step_static(const hydro_block_desc *blocks, int32_t nblocks, int32_t ndim, double *arena,
+                               int64_t arena_len, int32_t precision, double dt, double gamma, void *stream) {
+  if (nblocks > kStaticMaxBlocks)
+    return failf(HYDRO_EINVAL, "static step: %d blocks, at most %d", (int)nblocks, kStaticMaxBlocks);
+  std::pair<int64_t, int64_t> ranges[kStaticMaxBlocks];
+  hydro_status st = validate_blocks(blocks, nblocks, ndim, arena, arena_len, ranges);
+  if (st) return st;
+  if (!prec_valid(precision)) return failf(HYDRO_EINVAL, "static step: bad precision");
+  if (!finite_pos(dt)) return failf(HYDRO_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(gamma) || gamma <= 1.0) return failf(HYDRO_EINVAL, "gamma must be finite and > 1");
+  // scratch layout: time record | block table | work list | first-stage state
+  int64_t nitems = 0;
+  int kmask = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    bool t16 = false;
+    nitems += static_items_of(blocks[b], &t16);
+    kmask |= t16 ? 1 : 2;
+  }
+  const size_t off_blocks = align_up(sizeof(DevTime));
+  const size_t off_items = off_blocks + align_up((size_t)nblocks * sizeof(DevBlock));
+  const size_t off_u1 = off_items + align_up((size_t)nitems * sizeof(WorkItem));
+  const size_t need = off_u1 + (size_t)arena_len * sizeof(double);
+  if (need > kStaticScratchBytes || nitems > INT_MAX)
+    return failf(HYDRO_EINVAL,
+                 "static step: the mesh needs %zu bytes of scratch (first-stage state of arena_len doubles plus "
+                 "tables); the static scratch holds %zu",
+                 need, kStaticScratchBytes);
+  int dev = 0;
+  HIP_TRYF(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return failf(HYDRO_EDEVICE, "static step: device %d out of range", dev);
+  void *base = g_scratch_addr[dev].load(std::memory_order_acquire);
+  if (!base) {  // first call on this device: look up this GPU's copy of the array
+    void *p = nullptr;
+    HIP_TRYF(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return failf(HYDRO_EDEVICE, "static step: no device address for the scratch array");
+    g_scratch_addr[dev].store(p, std::memory_order_release);
+    base = p;
+  }
+  unsigned char *sb = static_cast<unsigned char *>(base);
+  DevTime *d_time = reinterpret_cast<DevTime *>(sb);
+  DevBlock *d_blocks = reinterpret_cast<DevBlock *>(sb + off_blocks);
+  WorkItem *d_items = reinterpret_cast<WorkItem *>(sb + off_items);
+  double *d_u1 = reinterpret_cast<double *>(sb + off_u1);
+  hipStream_t s = (hipStream_t)stream;
+
+  SetupChunk chunk;
+  int32_t item0 = 0;
+  for (int b0 = 0; b0 < nblocks; b0 += kSetupChunk) {
+    std::memset(&chunk, 0, sizeof(chunk));
+    chunk.count = std::min(kSetupChunk, nblocks - b0);
+    for (int g = 0; g < chunk.count; ++g) {
+      const int b = b0 + g;
+      bool t16 = false;
+      chunk.blk[g] = make_devblock(blocks, b, ndim);
+      chunk.id[g] = b;
+      chunk.item0[g] = item0;
+      item0 += static_items_of(blocks[b], &t16);
+    }
+    hipLaunchKernelGGL(k_static_setup, dim3(chunk.count), dim3(256), 0, s, chunk, d_blocks, d_items);
+    HIP_TRYF(hipGetLastError());
+  }
+  StageArgs a;
+  a.blocks = d_blocks;
+  a.items = d_items;
+  a.nitems = (int32_t)nitems;
+  a.reset_time = 1;  // stage 1 clears the time record's accumulators
+  a.xcd_remap = 1;
+  a.src = arena;
+  a.un = arena;
+  a.dst = d_u1;
+  a.dt = dt;
+  a.dt_dev = nullptr;
+  a.acc = d_time;
+  a.gamma = gamma;
+  const bool mixed = is_mixed(precision);
+  HIP_TRYF(hyd::launch_stage(ndim, mixed, 1, kmask, speeds_of(precision), recon_of(precision), eos_of(precision),
+                             (int)nitems, s, a));
+  a.reset_time = 0;
+  a.src = d_u1;
+  a.dst = arena;
+  HIP_TRYF(hyd::launch_stage(ndim, mixed, 2, kmask, speeds_of(precision), recon_of(precision), eos_of(precision),
+                             (int)nitems, s, a));
+  return HYDRO_OK;
 }
 
 }  // extern "C"

@@ -87,6 +87,7 @@ def lib():
             "hydro_stream_create": [C.POINTER(BlockDesc), i32, i32, vp, i64, C.POINTER(C.c_int32), i32, i32, i32, pp],
             "hydro_stream_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
             "hydro_stream_destroy": [vp],
+            "hydro_step_static": [C.POINTER(BlockDesc), i32, i32, vp, i64, i32, dbl, dbl, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -315,6 +316,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def step_static(block_mesh, arena, precision: int, dt: float, gamma: float, stream=None):
+    """One SSP-RK2 step of every block of `block_mesh` on the device arena (a
+    contiguous float64 CUDA tensor) through the allocation-free entry point:
+    the library's fixed scratch array holds every temporary."""
+    import torch
+
+    if arena.dtype != torch.float64 or not arena.is_cuda or not arena.is_contiguous():
+        raise ValueError("arena must be a contiguous float64 CUDA tensor")
+    descs = descs_from_mesh(block_mesh)
+    _check(lib().hydro_step_static(descs, len(descs), int(block_mesh.ndim), C.c_void_p(arena.data_ptr()),
+                                   arena.numel(), int(precision), float(dt), float(gamma),
+                                   C.c_void_p(_stream_handle(stream))), "hydro_step_static")
 
 
 class HostStream:

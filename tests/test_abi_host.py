@@ -173,3 +173,31 @@ def test_extent_and_count_limits_rejected_on_host():
     descs = H.descs_from_mesh(good())
     h = C.c_void_p()
     assert H.lib().hydro_mesh_create(descs, 0, 3, FAKE_ARENA, 100, None, C.byref(h)) == H.EINVAL
+
+
+def test_static_step_rejects_on_host():
+    """The allocation-free step checks sizes and arguments on the host before
+    any device work: a mesh beyond the fixed scratch, too many blocks, a bad
+    descriptor, dt or precision are EINVAL with a message."""
+    lib = H.lib()
+
+    def call(m, prec=H.FP64, dt=1e-3, gamma=1.4):
+        descs = H.descs_from_mesh(m)
+        rc = lib.hydro_step_static(descs, len(descs), m.ndim, FAKE_ARENA, m.arena_len, prec, dt, gamma, None)
+        return rc, lib.hydro_last_error().decode()
+
+    big = I.block_grid((8, 8, 8), (16, 16, 16), (0, 0, 0), (1, 1, 1), "periodic", 3)  # 80 MiB of stage state
+    rc, msg = call(big)
+    assert rc == H.EINVAL and "scratch" in msg, msg
+    rc, msg = call(I.independent_blocks([8] * 4097, 3))
+    assert rc == H.EINVAL and "4096" in msg, msg
+    m = good()
+    m.n[0, 0] = 12
+    rc, msg = call(m)
+    assert rc == H.EINVAL and "multiples of 8" in msg, msg
+    rc, msg = call(good(), dt=float("nan"))
+    assert rc == H.EINVAL and "dt" in msg, msg
+    rc, msg = call(good(), gamma=1.0)
+    assert rc == H.EINVAL and "gamma" in msg, msg
+    rc, msg = call(good(), prec=7)
+    assert rc == H.EINVAL and "precision" in msg, msg
