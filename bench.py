@@ -14,12 +14,17 @@ Timed paths (same input, state reset between them):
                       blocks) and a host reduce_dt per packet each step.
 
 Metric: cell-updates/s (interior cells x steps / wall time, inputs resident in
-HBM).  Roofline: HBM, 200 algorithmic bytes per cell-update (FP64 state, five
-state passes: stage 1 reads Un and writes U1, stage 2 reads U1 and Un and
-writes Un+1), 8.0 TB/s peak; the stage kernel's launch durations are measured
-with HIP events on the mesh stream.  Errors vs the FP64 oracle are measured on
-sampled blocks after one step from the initial state.  cpu_baseline: the
-oracle (plain FP64 C, OpenMP) on a bounded sample of the same workload.
+HBM); the timed region (K steps) is repeated (5 times by default) and the
+median is reported.  Roofline: HBM, 200 algorithmic bytes per cell-update
+(FP64 state, five state passes: stage 1 reads Un and writes U1, stage 2 reads
+U1 and Un and writes Un+1), 8.0 TB/s peak, over the step's device time (HIP
+events on the mesh stream around every graph replay) and over the wall time;
+per stage kernel over its own launch duration.  The practical ceiling comes
+from a sweep of plain streaming kernels (copy, read, write; elements in
+flight; workgroups per CU; 2 and 8 GiB buffers).  Errors vs the FP64 oracle
+after K steps on the centred 512-block subset (the oracle runs the region
+that holds its domain of dependence).  cpu_baseline: that oracle run (plain
+FP64 C, OpenMP, all host cores) and a one-core run of the subset.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|smooth|uneven|sedov]
 """
@@ -133,26 +138,58 @@ def oracle_region_run(P, steps):
     cpu = {"value": cells * steps / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
            "host": host_cpu(), "sample": f"{len(ids)} blocks ({cells} cells) around the centred {len(P.meta['subset'])}-block subset "
                      f"of the same workload, {steps} steps, {el:.1f} s"}
+    cpu["one_core"] = oracle_one_core(P)
     return ids, m, U, dts, cpu
 
 
+def oracle_one_core(P, steps=2):
+    """The oracle on one thread: the centred subset as its own mesh (links
+    that leave it wrap), `steps` steps from the initial state."""
+    from oracle import oracle as O
+
+    ids = np.asarray(P.meta["subset"])
+    m = P.mesh.subset(ids)
+    U = P.mesh.gather(P.U0, ids)
+    nthreads = O.num_threads()
+    O.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run(m, U, steps, P.cfl, P.gamma)
+        el = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(nthreads)
+    return {"value": m.total_cells * steps / el, "unit": "cell-updates/s", "cores": 1,
+            "sample": f"the centred {len(ids)}-block subset ({m.total_cells} cells) as its own mesh, {steps} steps, "
+                      f"{el:.1f} s"}
+
+
 def host_cpu() -> str:
-    """The host CPU's model name and the logical CPUs this process may use."""
-    model = "unknown CPU"
+    """The host CPU's model name (with family, model and stepping numbers) and
+    the logical CPUs the machine has and this process may use."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = (x.strip() for x in line.split(":", 1))
+                    if k in ("model name", "cpu family", "model", "stepping", "vendor_id") and k not in info:
+                        info[k] = v
+                if not line.strip() and info:
                     break
     except OSError:
         pass
-    return f"{model}, {len(os.sched_getaffinity(0))} logical CPUs available"
+    model = info.get("model name", "unknown CPU")
+    ids = ", ".join(f"{k} {info[k]}" for k in ("vendor_id", "cpu family", "model", "stepping") if k in info)
+    return (f"{model} ({ids}); {os.cpu_count()} logical CPUs on the host, "
+            f"{len(os.sched_getaffinity(0))} available to this process")
 
 
 def subset_errors(P, ids, m, Uref, U_gpu_sub):
     """Errors of GPU states (arrays of the subset blocks, subset layout) vs the
-    oracle's region run on the centred subset."""
+    oracle's region run on the centred subset: over every subset cell, and
+    L1(rho) over only the cells whose density the oracle changed (the rest is
+    gas at rest at uniform pressure, which the scheme leaves exactly as it
+    was, so it dilutes the figure)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from gpu_util import l1_rho, rel_err
 
@@ -160,44 +197,81 @@ def subset_errors(P, ids, m, Uref, U_gpu_sub):
     inner = [pos[int(b)] for b in P.meta["subset"]]
     ms = m.subset(inner)
     R = m.gather(Uref, inner)
-    return {"max_rel_err": rel_err(ms, U_gpu_sub, R), "l1_rho_rel": l1_rho(ms, U_gpu_sub, R)}
+    R0 = P.mesh.gather(P.U0, P.meta["subset"])
+    nb = len(inner)
+    rho_ref = R.reshape(nb, 5, -1)[:, 0]
+    rho_gpu = U_gpu_sub.reshape(nb, 5, -1)[:, 0]
+    changed = rho_ref != R0.reshape(nb, 5, -1)[:, 0]
+    l1c = float(np.abs(rho_gpu - rho_ref)[changed].sum() / np.abs(rho_ref)[changed].sum()) if changed.any() else 0.0
+    return {"max_rel_err": rel_err(ms, U_gpu_sub, R), "l1_rho_rel": l1_rho(ms, U_gpu_sub, R),
+            "l1_rho_rel_changed_cells": l1c, "changed_cells": int(changed.sum()), "cells": int(changed.size)}
 
 
-def copy_bandwidth(n_doubles=1 << 28, reps=5):
-    """GB/s of the project's plain stream-copy kernels on two 2 GiB buffers
-    (far larger than the 256 MB last-level cache): read + write bytes / time,
-    best of the two kernel forms."""
+PROBE_MODES = {0: "copy", 1: "copy_nt", 2: "read", 3: "write"}
+
+
+def copy_bandwidth(sizes=(1 << 28, 1 << 30), reps=5):
+    """HBM bandwidth of the project's plain streaming kernels: copy (plain
+    and nontemporal), read-only and write-only, each with 1, 2, 4 or 8
+    16-byte elements per thread in flight and 2 to 32 workgroups per CU, on
+    buffers of 2 GiB and 8 GiB (far larger than the 256 MB last-level cache).
+    Bytes moved (read + written) / time.  Returns the best of each kind with
+    its configuration; `gbs` is the best copy, the ceiling the stage kernels
+    (which read and write) are compared with."""
     import ctypes as C
 
     import torch
 
     lib = C.CDLL(os.path.join(ROOT, "paper_2507_09337_amd", "libhydro_probe.so"))
-    lib.copy_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_int,
-                               C.POINTER(C.c_double)]
-    src = torch.ones(n_doubles, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    out = {"bytes_per_copy": 16 * n_doubles}
-    for form in (0, 1):
-        ms = C.c_double(0.0)
-        dst.zero_()
-        rc = lib.copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n_doubles,
-                            C.c_void_p(torch.cuda.current_stream().cuda_stream), reps, form, C.byref(ms))
-        if rc != 0:
-            raise RuntimeError(f"copy_probe failed with {rc}")
-        out[f"form{form}_gbs"] = 2 * 8 * n_doubles / (ms.value * 1e-3) / 1e9
-        out[f"form{form}_verified"] = bool(torch.equal(src, dst))
-    out["gbs"] = max(out["form0_gbs"], out["form1_gbs"])
-    del src, dst
-    torch.cuda.empty_cache()
-    return out
+    lib.stream_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                 C.POINTER(C.c_double)]
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    best = {}
+    table = []
+    for n in sizes:
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for mode, kind in PROBE_MODES.items():
+            for elems in (1, 2, 4, 8):
+                for wg in (2, 4, 8, 16, 32):
+                    ms = C.c_double(0.0)
+                    rc = lib.stream_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n, stream, reps,
+                                          mode, elems, wg, C.byref(ms))
+                    if rc != 0:
+                        raise RuntimeError(f"stream_probe failed with {rc}")
+                    nbytes = 8 * n * (2 if mode in (0, 1) else 1)
+                    gbs = nbytes / (ms.value * 1e-3) / 1e9
+                    rec = {"kind": kind, "bytes": 8 * n, "elems_in_flight": elems, "wg_per_cu": wg, "gbs": gbs}
+                    table.append(rec)
+                    if kind not in best or gbs > best[kind]["gbs"]:
+                        best[kind] = rec
+            if mode in (0, 1):  # the copies must be exact
+                assert torch.equal(src, dst), f"copy probe mode {mode} wrote wrong data"
+        del src, dst
+        torch.cuda.empty_cache()
+    copy = max((best["copy"], best["copy_nt"]), key=lambda r: r["gbs"])
+    return {"gbs": copy["gbs"], "best_copy": copy, "best_read": best["read"], "best_write": best["write"],
+            "configs": len(table), "table": table}
+
+
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_09337_amd", "csrc", f)
+                  for f in ("stage_kernels.h", "kernels_inst.hip", "hydro_internal.h")]
+
+
+def kernel_source_sha() -> str:
+    """SHA-256 over the stage kernels' source files (their device code)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel_names):
     """HBM bytes per step of the given stage kernels from the committed
     rocprofv3 counter summary, or None when the summary is missing or was
     taken on a different version of the kernel source."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "stage_kernels_large.md")
     if not os.path.exists(path):
         return None
@@ -205,10 +279,7 @@ def measured_traffic(kernel_names):
     for line in open(path):
         if line.startswith("TRAFFIC_JSON "):
             rec = json.loads(line[len("TRAFFIC_JSON "):])
-    if not rec:
-        return None
-    src = os.path.join(ROOT, "paper_2507_09337_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernels_sha256"]:
+    if not rec or rec.get("kernels_sha256") != kernel_source_sha():
         return None
     total = 0.0
     for k in kernel_names:
@@ -217,6 +288,87 @@ def measured_traffic(kernel_names):
             return None
         total += t["fetch_bytes"] + t["write_bytes"]
     return total
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_profiles(args):
+    """Markdown summary of three rocprofv3 runs of this benchmark on the
+    large workload (kernel trace with --stats; PMC FETCH_SIZE; PMC
+    WRITE_SIZE), written to stdout.  The counters are scaled by what they
+    read for the plain copy kernel of the streaming probe (known bytes).  A
+    TRAFFIC_JSON line at the end feeds the benchmark's roofline.traffic."""
+    cells = 32768 * 4096
+    stats = _csv_rows(args.kt, "kernel_stats.csv")
+    lines = ["# Stage kernels on the large workload (32768 blocks of 16^3 = 134217728 cells)", "",
+             "Workload: Sedov deposit + 1 % density noise, periodic, gamma 1.4, CFL 0.4; batched launches (one "
+             "per RK stage over all 512 packets).", "", "## Commands", "", "```", "cd /tmp && export TMPDIR=/tmp"]
+    lines += [c for c in args.cmd] + ["```", "", "## Kernel trace summary (rocprofv3 --stats)", "",
+                                      "| Kernel | Calls | Average ns | Min ns | Max ns | % |", "|---|---|---|---|---|---|"]
+    avg = {}
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        avg[r["Name"]] = float(r["AverageNs"])
+        lines.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']):.0f} | {float(r['MinNs']):.0f} | "
+                     f"{float(r['MaxNs']):.0f} | {float(r['Percentage']):.3g} |")
+    s1 = "void hyd::k_stage<3, true, 1, 1, 0, 0, 0, 0>(hyd::StageArgs)"
+    s2 = "void hyd::k_stage<3, true, 2, 1, 0, 0, 0, 0>(hyd::StageArgs)"
+    if s1 in avg and s2 in avg:
+        t = (avg[s1] + avg[s2]) * 1e-9
+        lines += ["", f"Headline kernels (mixed, Davis, primitive PLM): stage 1 {avg[s1] / 1e6:.3f} ms + stage 2 "
+                      f"{avg[s2] / 1e6:.3f} ms = {t * 1e3:.3f} ms per step; 200 B x {cells} cells / that = "
+                      f"{200 * cells / t / 1e9:.0f} GB/s = {200 * cells / t / 1e9 / HBM_PEAK_GBS:.3f} of 8 TB/s; "
+                      f"stage 2 alone {120 * cells / (avg[s2] * 1e-9) / 1e9 / HBM_PEAK_GBS:.3f} (120 B)."]
+    per = {}
+    for kind, d in (("fetch", args.fetch), ("write", args.write)):
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = r.get("Kernel_Name", "")
+            per.setdefault(name, {}).setdefault(kind, []).append(float(r["Counter_Value"]))
+    calib = "k_copy_e<1, false>"
+    cname = next((n for n in per if calib in n), None)
+    if cname and per:
+        # the probe's copies of 2 GiB buffers (2 GiB read and 2 GiB written per launch) are the smallest of
+        # its dispatches of this kernel (the 8 GiB ones read four times as much)
+        copy_bytes = 8 * (1 << 28)
+
+        def small(vals):
+            lo = min(vals)
+            return float(np.median([v for v in vals if v <= 1.1 * lo]))
+
+        fkib = small(per[cname]["fetch"])
+        wkib = small(per[cname]["write"])
+        ff, wf = copy_bytes / (fkib * 1024), copy_bytes / (wkib * 1024)
+        lines += ["", "## HBM traffic (PMC FETCH_SIZE, WRITE_SIZE)", "",
+                  f"Calibration with the plain copy kernel `{cname}` moving {copy_bytes} B each way (2 GiB buffers): "
+                  f"FETCH_SIZE reads {fkib:.1f} KiB, WRITE_SIZE {wkib:.1f} KiB per dispatch, so bytes = KiB x 1024 x "
+                  f"{ff:.4f} (fetch) and x {wf:.4f} (write).", "",
+                  "| Kernel | Fetch B/launch | Write B/launch | Fetch B/cell | Write B/cell | Algorithmic B/cell |",
+                  "|---|---|---|---|---|---|"]
+        rec = {"kernels_sha256": kernel_source_sha(), "cells": cells, "fetch_factor": ff, "write_factor": wf,
+               "per_launch": {}}
+        for name, v in per.items():
+            if "k_stage<3" not in name or "fetch" not in v or "write" not in v:
+                continue
+            fb = float(np.mean(v["fetch"])) * 1024 * ff
+            wb = float(np.mean(v["write"])) * 1024 * wf
+            targs = name[name.index("<") + 1:name.index(">")].split(", ")
+            alg = 80 if targs[2] == "1" else 120  # k_stage<DIM, MIXED, STAGE, ...>
+            rec["per_launch"][name] = {"fetch_bytes": fb, "write_bytes": wb}
+            lines.append(f"| `{name}` | {fb:.4g} | {wb:.4g} | {fb / cells:.1f} | {wb / cells:.1f} | {alg} |")
+        lines += ["", f"Kernel sources (stage_kernels.h, kernels_inst.hip, hydro_internal.h) sha256 at measurement: "
+                      f"`{rec['kernels_sha256']}`", "", "TRAFFIC_JSON " + json.dumps(rec)]
+    if args.bench_line:
+        lines += ["", "## The benchmark line of the kernel-trace run", "", "```", open(args.bench_line).read().strip(),
+                  "```"]
+    print("\n".join(lines))
 
 
 def host_packets_bench(args):
@@ -243,6 +395,24 @@ def host_packets_bench(args):
                                             "ms_per_step": 1e3 * el / args.steps,
                                             "pcie_gbs": 80.0 * cells * args.steps / el / 1e9}
             log(name, nslots, json.dumps(out[f"{name}_slots{nslots}"]))
+    # CPU/GPU split (the paper's blocks-per-cycle split between host cores and GPU): the last k packets on
+    # the host cores, the rest streamed through four GPU slots
+    split = {}
+    nthreads = len(os.sched_getaffinity(0))
+    for prec, name in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
+        for k in (0, 4, 8, 16, 24, 32, 48):
+            host = torch.from_numpy(P.U0.copy()).pin_memory()
+            hs = H.HostStream(P.mesh, host, P.packets, prec, 4)
+            hs.set_cpu_share(k, nthreads)
+            hs.run(args.warmup, P.cfl, P.gamma)
+            ts = time.perf_counter()
+            hs.run(args.steps, P.cfl, P.gamma)
+            el = time.perf_counter() - ts
+            hs.close()
+            cpu_cells = int(sum(P.mesh.ncells[np.asarray(p)].sum() for p in P.packets[len(P.packets) - k:])) if k else 0
+            split[f"{name}_cpu{k}"] = {"cpu_packets": k, "cpu_cells": cpu_cells, "cpu_threads": nthreads,
+                                       "cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps}
+            log(name, "split", k, json.dumps(split[f"{name}_cpu{k}"]))
     best = max((v for k, v in out.items() if k.startswith("mixed")), key=lambda v: v["cell_updates_per_s"])
     print(json.dumps({"metric": "cell-updates/s, host-resident packets (PCIe-inclusive), uneven workload, 1 MI355X",
                       "value": best["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
@@ -251,7 +421,45 @@ def host_packets_bench(args):
                       "dtype": "f32 (PLM+HLLC) / f64 (state, recovery, update, dt)", "data": "synthetic (seeded)",
                       "config": {"workload": f"uneven: {P.mesh.nblocks} self-periodic blocks, {cells} cells, "
                                              f"{len(P.packets)} packets, state in pinned host memory"},
-                      "paths": out}), flush=True)
+                      "paths": out, "cpu_gpu_split": split}), flush=True)
+
+
+def fused_class_study(P, steps, warmup):
+    """The communication-avoiding fused step on the self-periodic 8^3 blocks
+    of the uneven workload: those blocks as their own mesh, advanced by the
+    two stage launches (200 algorithmic B per cell-update: U1 written and read
+    back) and by the fused kernel (80 B: the block stays on chip between the
+    stages), in both precisions; and the whole workload with the 8^3 class
+    fused.  Device time per step from HIP events around the graph replays."""
+    import torch
+
+    from paper_2507_09337_amd import hydro as H
+
+    ids = np.nonzero(P.mesh.n[:, 0] == 8)[0]
+    m = P.mesh.subset(ids)
+    U0 = torch.from_numpy(P.mesh.gather(P.U0, ids)).cuda()
+    cells = m.total_cells
+    out = {"blocks": int(ids.size), "cells": int(cells)}
+    for prec, pname in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
+        for fused in (False, True):
+            arena = U0.clone()
+            mesh = H.Mesh(m, arena)
+            b = H.Batch([H.Packet(mesh, range(m.nblocks), prec)])
+            if fused:
+                b.set_tiling(8, 5)
+            b.run(warmup, P.cfl, P.gamma)
+            _, ms = b.run_timed(steps, P.cfl, P.gamma)
+            dev = float(np.median(ms))
+            alg = 80.0 if fused else 200.0
+            out[f"{pname}_{'fused' if fused else 'two_launch'}"] = {
+                "device_ms_per_step": dev, "cell_updates_per_s": cells / (dev * 1e-3),
+                "algorithmic_bytes_per_cell_update": alg,
+                "achieved_gbs": alg * cells / (dev * 1e-3) / 1e9,
+                "frac_of_hbm": alg * cells / (dev * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "gbs_at_200B": 200.0 * cells / (dev * 1e-3) / 1e9}
+            mesh.close()
+            log("fused study", pname, fused, json.dumps(out[f"{pname}_{'fused' if fused else 'two_launch'}"]))
+    return out
 
 
 def main():
@@ -259,6 +467,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5, help="repetitions of the timed region (median reported)")
+    ap.add_argument("--no-probe", action="store_true", help="skip the HBM streaming-kernel sweep")
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-packet FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -267,7 +477,16 @@ def main():
     ap.add_argument("--host-packets", action="store_true",
                     help="instead: host-resident packets of the uneven workload streamed through device slots "
                          "(PCIe-inclusive rate; prints its own line)")
+    ap.add_argument("--summarize-profiles", action="store_true",
+                    help="instead: write the markdown summary of rocprofv3 runs (--kt, --fetch, --write dirs)")
+    ap.add_argument("--kt", help="rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output directory")
+    ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output directory")
+    ap.add_argument("--cmd", action="append", default=[], help="command line to list in the summary")
+    ap.add_argument("--bench-line", help="file holding the JSON line of the kernel-trace run")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        return summarize_profiles(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
               file=sys.stderr)
@@ -282,8 +501,9 @@ def main():
     torch.cuda.set_device(0)
     if args.host_packets:
         return host_packets_bench(args)
-    probe = copy_bandwidth()
-    log("copy probe:", json.dumps(probe))
+    probe = None if args.no_probe else copy_bandwidth()
+    if probe:
+        log("HBM streaming probe:", json.dumps({k: v for k, v in probe.items() if k != "table"}))
     t0 = time.perf_counter()
     P = make_problem(args.workload)
     cells = P.mesh.total_cells
@@ -312,13 +532,18 @@ def main():
         if args.tune:
             b.autotune(P.gamma, reps=3)
         b.run(args.warmup, P.cfl, P.gamma)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        _, step_ms = b.run_timed(args.steps, P.cfl, P.gamma)  # HIP events around every graph replay
-        torch.cuda.synchronize()
-        el = time.perf_counter() - ts
-        results[name] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-                         "device_ms_per_step": float(np.mean(step_ms)), "config": b.config()}
+        reps = []
+        for _ in range(args.repeats):  # the timed region, repeated; the median is reported
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, step_ms = b.run_timed(args.steps, P.cfl, P.gamma)  # HIP events around every graph replay
+            torch.cuda.synchronize()
+            el = time.perf_counter() - ts
+            reps.append({"wall_ms_per_step": 1e3 * el / args.steps, "device_ms_per_step": float(np.mean(step_ms))})
+        wall = float(np.median([r["wall_ms_per_step"] for r in reps]))
+        dev = float(np.median([r["device_ms_per_step"] for r in reps]))
+        results[name] = {"cell_updates_per_s": cells / (wall * 1e-3), "ms_per_step": wall,
+                         "device_ms_per_step": dev, "repeats": reps, "config": b.config()}
         # kernel durations: `steps` eager steps from the initial state
         arena.copy_(U0_dev)
         kernel_ms[name] = b.time_kernels(args.steps, P.cfl, P.gamma)
@@ -329,6 +554,26 @@ def main():
                                                   5 * int(P.mesh.ncells[i])].cpu().numpy()
                                             for i in P.meta["subset"]])
         log(name, json.dumps(results[name]), json.dumps(kernel_ms[name]))
+
+    fused_study = None
+    if P.name == "uneven":  # the whole workload with the 8^3 class on the fused step, and that class alone
+        for name, pks in (("batched_mixed_fused8", pkmx), ("batched_fp64_fused8", pk64)):
+            arena.copy_(U0_dev)
+            b = H.Batch(pks)
+            if args.tune:
+                b.autotune(P.gamma, reps=3)
+            b.set_tiling(8, 5)
+            b.run(args.warmup, P.cfl, P.gamma)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, step_ms = b.run_timed(args.steps, P.cfl, P.gamma)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - ts
+            results[name] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                             "device_ms_per_step": float(np.mean(step_ms)), "config": b.config()}
+            b.close()
+            log(name, json.dumps(results[name]))
+        fused_study = fused_class_study(P, args.steps, args.warmup)
 
     # method variants (Einfeldt, PVRS wave speeds; conserved, characteristic PLM; gas + radiation EOS):
     # kernel time of a few eager steps
@@ -394,10 +639,19 @@ def main():
 
     head = results["batched_mixed"]
     km = kernel_ms["batched_mixed"]
-    step_dev_ms = head["device_ms_per_step"]  # the step graph's device time over the timed region
+    step_dev_ms = head["device_ms_per_step"]  # the step graph's device time over the timed region (median)
     achieved = BYTES_PER_CELL_UPDATE * cells / (step_dev_ms * 1e-3) / 1e9
-    traffic = measured_traffic(["void hyd::k_stage<3, true, 1, 1, 0, 0, 0>(hyd::StageArgs)",
-                                "void hyd::k_stage<3, true, 2, 1, 0, 0, 0>(hyd::StageArgs)"]) if P.name == "sedov_noise" else None
+    achieved_wall = BYTES_PER_CELL_UPDATE * cells / (head["ms_per_step"] * 1e-3) / 1e9
+    occ = head["config"].get("occupancy", 0)
+    names = {1: f"void hyd::k_stage<3, true, 1, 1, 0, 0, 0, {occ}>(hyd::StageArgs)",
+             2: f"void hyd::k_stage<3, true, 2, 1, 0, 0, 0, {occ}>(hyd::StageArgs)"}
+    traffic = measured_traffic([names[1], names[2]]) if P.name == "sedov_noise" else None
+    per_kernel = {}
+    for st, alg in ((1, 80.0), (2, 120.0)):
+        ms = km[f"stage{st}_ms"]
+        per_kernel[f"stage{st}"] = {"kernel": names[st], "ms": ms, "algorithmic_bytes_per_cell": alg,
+                                    "achieved_gbs": alg * cells / (ms * 1e-3) / 1e9,
+                                    "frac": alg * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     roofline = {
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
@@ -405,15 +659,21 @@ def main():
                         "copy-kernel calibration, from profiles/stage_kernels_large.md (null if the kernel source "
                         "changed since)",
         "kernel": "k_stage stage-1 + stage-2 launches of one step (80 + 120 algorithmic B per interior cell); "
-                  "duration = mean device time of the replayed step graph (both stage kernels and the dt update) "
-                  "over the timed region, from HIP events on the mesh stream around every replay",
+                  "duration = device time of the replayed step graph (both stage kernels and the dt update) from "
+                  "HIP events on the mesh stream around every replay, mean over the timed region, median over "
+                  f"{args.repeats} repetitions",
         "step_device_ms": step_dev_ms,
-        "stage1_ms": km["stage1_ms"], "stage2_ms": km["stage2_ms"],
-        "stage_ms_note": "stage1_ms / stage2_ms: mean HIP-event durations of the same kernels launched eagerly "
-                         "for `steps` steps right after the timed region (the split between the two launches)",
+        "frac_wall": achieved_wall / HBM_PEAK_GBS,
+        "frac_wall_note": "the same 200 B per cell-update over the wall-clock ms_per_step (includes the first dt "
+                          "reduction of each timed run and the final read-back)",
+        "per_kernel": per_kernel,
+        "per_kernel_note": "eager launches of the same kernels with HIP events around each, for `steps` steps "
+                           "right after the timed region; stage 2 (120 B) is the dominant kernel",
         "algorithmic_bytes_per_step": BYTES_PER_CELL_UPDATE * cells,
-        "copy_probe_gbs": probe["gbs"], "frac_of_copy_probe": achieved / probe["gbs"],
     }
+    if probe:
+        roofline.update({"copy_probe_gbs": probe["gbs"], "frac_of_copy_probe": achieved / probe["gbs"],
+                         "hbm_ceiling": {k: probe[k] for k in ("best_copy", "best_read", "best_write", "configs")}})
     ach64 = BYTES_PER_CELL_UPDATE * cells / (results["batched_fp64"]["device_ms_per_step"] * 1e-3) / 1e9
 
     line = {
@@ -440,6 +700,7 @@ def main():
         "tuning": results["batched_mixed"]["config"],
         "errors_vs_oracle": errs,
         "variants_kernel_time": variants,
+        "fused_8cube_class": fused_study,
     }
     if "plain_fp64" in results:
         line["speedup_vs_plain_fp64"] = head["cell_updates_per_s"] / results["plain_fp64"]["cell_updates_per_s"]
