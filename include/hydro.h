@@ -267,6 +267,15 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  *               linked along +z within the batch, whole blocks, 3D); the
  *               mixed-precision tile marches through the run without
  *               re-reading the z halo of each block;
+ *           5 = fused step (edge 8 only; every block of the class 3D, 8^3,
+ *               periodic on itself on all six faces; HYDRO_FP64 or
+ *               HYDRO_FP32_FP64 without variants): one workgroup takes a
+ *               whole block through both RK stages with the block on chip,
+ *               so Un is read and Un+1 written once per step and the
+ *               first-stage state never goes to memory (80 instead of 200
+ *               bytes per cell-update; the communication-avoiding step of
+ *               the paper's Sec. 6 for blocks whose halo is their own
+ *               interior);
  *   zchunk: z planes per work item (0 = the whole block; 3D only).
  * Without a setting a class uses 16x16 tiles (8x8 if its extents need them)
  * on whole blocks, in z-runs of two when the class has at least 12 x (number
@@ -280,7 +289,8 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * neighbouring blocks' guard reads in one L2 (0 = hardware order).
  * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_launch
  * rebuild or relaunch accordingly (EINVAL for a tile the class cannot use, or
- * a value out of range).  hydro_batch_autotune times every candidate tiling of
+ * a value out of range, or a fused step the class cannot take).
+ * hydro_batch_autotune times every candidate tiling of
  * every class present (the median device time of a stage-1 and of a stage-2
  * launch on the class's own blocks, summed; both write only the mesh's
  * scratch stage buffer, never the arena: stage 2 takes its stencil from the
@@ -288,13 +298,23 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * rejects a candidate whose stage-1 or stage-2 result (stage 2 run with the
  * arena as stencil and Un) differs from the default tiling's by more than
  * 1e-13 relative (FP64) or 1e-6 (mixed) on up to 64 blocks, keeps the
- * fastest, then picks grid and xcd_remap the same way.  reps = timed launches per candidate
- * (>= 1).  Synchronising.  hydro_batch_get_config writes grid to out[0],
- * xcd_remap to out[1], then (edge, tile, zchunk, ncells_in_class_low31) for
- * each class from out[2], up to nclass_max classes (out holds 2 + 4 *
- * nclass_max int32); *nclass receives the number of classes. */
+ * fastest, then picks grid and xcd_remap the same way; a class the fused
+ * step can take gets it when its full step on a copy of the sample matches
+ * the default tiling's and the whole batch step (all launches) is faster
+ * with it.  reps = timed launches per candidate
+ * (>= 1).  Synchronising.  hydro_batch_set_occupancy(b, waves) asks the
+ * stage kernels of the batch's launches for the register budget of `waves`
+ * (2, 3 or 4) waves per SIMD instead of their own (0); only for HYDRO_FP64 or
+ * HYDRO_FP32_FP64 without variants (EINVAL otherwise); the autotuner tries 2,
+ * 3 and 4 after the launch shape, parity-checked like the tilings.
+ * hydro_batch_get_config writes grid to out[0], xcd_remap to out[1], the
+ * occupancy request to out[2], then (edge, tile, zchunk,
+ * ncells_in_class_low31) for each class from out[3], up to nclass_max
+ * classes (out holds 3 + 4 * nclass_max int32); *nclass receives the number
+ * of classes. */
 hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk);
 hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_remap);
+hydro_status hydro_batch_set_occupancy(hydro_batch *b, int32_t waves);
 hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps);
 hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass);
 
@@ -302,7 +322,8 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
  * steps like hydro_batch_run but launches the two stage kernels eagerly (no
  * graph) on the mesh stream with HIP events around each launch, and returns
  * the mean duration in milliseconds of the stage-1 and stage-2 launches in
- * ms_out[0] and ms_out[1], and the summed wall time of all launches of the
+ * ms_out[0] and ms_out[1] (ms_out[1] includes the fused-step launch of
+ * classes tiled 5), and the summed wall time of all launches of the
  * step (stage 1 + stage 2 + finalize) per step in ms_out[2].  Same results in
  * the arena as hydro_batch_run.  Synchronising.
  * Errors: as hydro_batch_run. */
@@ -346,6 +367,21 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
  * result of the failing step and *t_out its end time.  Errors: EINVAL,
  * ENONPHYS, EDEVICE. */
 hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, double gamma, double *t_out);
+
+/* CPU/GPU split of a stream's packets (Sec. 6.1 and its Sedov table: a
+ * number of blocks per cycle goes to the host cores, the rest to the GPU,
+ * both at once).  The last cpu_packets packets (0..npackets; 0, the default,
+ * is GPU only) are advanced by nthreads host threads (0 = one per hardware
+ * thread) with a host kernel: FP64, Davis bounds, primitive PLM, gamma law,
+ * the FP64 GPU path's operations in its order (the same results bit for bit),
+ * in place in the host arena, while the GPU's slots stream the other packets.
+ * Each step the host reads the device dt (one synchronisation per step), runs
+ * both stages of its packets and folds their CFL rate and non-physical flag
+ * into the device accumulator before the dt update; failures follow
+ * hydro_stream_run's contract.  A stream whose precision code carries a
+ * method variant takes no host share (EINVAL); on a mixed-precision stream
+ * the host packets still compute in FP64.  Errors: EINVAL, ENOMEM. */
+hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, int32_t nthreads);
 
 hydro_status hydro_stream_destroy(hydro_stream *s);
 

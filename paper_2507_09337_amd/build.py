@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 # (source, extra flags): the stage-kernel instantiation unit is compiled once
 # per (dimension, mixed precision, stage), so the instantiations build in
 # parallel.
-SOURCES = [(os.path.join(CSRC, "kernels.hip"), []), (os.path.join(CSRC, "api.hip"), [])] + [
+SOURCES = [(os.path.join(CSRC, f), []) for f in ("kernels.hip", "api.hip", "host_step.hip")] + [
     (os.path.join(CSRC, "kernels_inst.hip"), [f"-DHYD_DIM={d}", f"-DHYD_MIXED={m}", f"-DHYD_STAGE={st}"])
     for d in (2, 3) for m in (0, 1) for st in (1, 2)
 ]

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <cfloat>
 #include <climits>
 #include <atomic>
 #include <cmath>
@@ -15,10 +16,12 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <utility>
 #include <vector>
 
+#include "host_step.h"
 #include "hydro.h"
 #include "hydro_internal.h"
 
@@ -54,9 +57,21 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 struct TileCfg {
   int tile = -1;   // -1: default (16x16 when the extents allow it); 0: 16x16; 1: 8x8;
-                   // 2..4: 16x16 in runs of that many blocks along +z
+                   // 2..4: 16x16 in runs of that many blocks along +z;
+                   // 5: fused step (self-periodic 8^3 blocks, both stages in one launch)
   int zchunk = 0;  // 0: whole block
 };
+
+constexpr int TILE_FUSED = 5;
+
+// A block the fused step can take: 3D, 8^3 interior cells, every face
+// periodic on the block itself.
+bool fusable(const hydro_block_desc &d, int ndim) {
+  if (ndim != 3 || d.n[0] != 8 || d.n[1] != 8 || d.n[2] != 8) return false;
+  for (int f = 0; f < 6; ++f)
+    if (d.face_kind[f] != HYDRO_PERIODIC_SELF) return false;
+  return true;
+}
 
 // Class of a block for tuning: its edge when the block is a square (2D) or a
 // cube (3D), else 0.
@@ -108,7 +123,10 @@ struct hydro_batch {
   std::map<int, TileCfg> cfg;
   int grid = 0;
   int remap = 1;
+  int occ = 0;  // waves per SIMD asked of the stage kernels (0 = their own budget)
   WorkList wl;
+  int32_t *d_fused = nullptr;  // blocks taken by the fused step (classes tiled TILE_FUSED)
+  int nfused = 0;
   DevTime *d_time = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -222,9 +240,10 @@ int default_run(const hydro_mesh *m, int64_t tiles) {
 // the second, ...), so the workgroups that run at the same time hold
 // neighbouring columns at the same height.
 void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std::map<int, TileCfg> &cfg,
-                 std::vector<WorkItem> &items, int &kmask) {
+                 std::vector<WorkItem> &items, int &kmask, std::vector<int32_t> *fused = nullptr) {
   items.clear();
   kmask = 0;
+  if (fused) fused->clear();
   std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> pending;
   auto emit8 = [&](std::vector<std::array<int, 3>> &q, int z0, int z1) {
     WorkItem it;
@@ -262,7 +281,9 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
     const hydro_block_desc &d = m->desc[b];
     const TileCfg c = cfg_of(b);
     const bool can16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
-    if (m->ndim != 3 || !can16 || c.tile == 1 || c.tile == 0 || (c.zchunk > 0 && c.zchunk < d.n[2])) return 1;
+    if (m->ndim != 3 || !can16 || c.tile == 1 || c.tile == 0 || c.tile == TILE_FUSED ||
+        (c.zchunk > 0 && c.zchunk < d.n[2]))
+      return 1;
     if (c.tile < 0) return default_run(m, class_tiles[block_class(d, m->ndim)]);
     return std::min(c.tile, 4);
   };
@@ -271,6 +292,10 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
     if (run_len(ids[i]) > 1) pos[ids[i]] = i;
   for (int32_t b : ids) {
     if (pos.count(b)) continue;
+    if (fused && cfg_of(b).tile == TILE_FUSED && fusable(m->desc[b], m->ndim)) {
+      fused->push_back(b);  // the fused step takes the whole block
+      continue;
+    }
     const hydro_block_desc &d = m->desc[b];
     const TileCfg c = cfg_of(b);
     const bool can16 = (d.n[0] % 16 == 0) && (d.n[1] % 16 == 0);
@@ -422,6 +447,23 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
+// Arguments of the batch's fused-step launch (one workgroup per fused block).
+hyd::FusedArgs fused_args(const hydro_mesh *m, const int32_t *ids, int n, double *state, double dt,
+                          const DevTime *dt_dev, DevTime *acc, double gamma, int rate_only, int remap) {
+  hyd::FusedArgs a;
+  a.blocks = m->d_blocks;
+  a.ids = ids;
+  a.nblocks = n;
+  a.rate_only = rate_only;
+  a.xcd_remap = remap;
+  a.state = state;
+  a.dt = dt;
+  a.dt_dev = dt_dev;
+  a.acc = acc;
+  a.gamma = gamma;
+  return a;
+}
+
 // A precision code: HYDRO_FP64 or HYDRO_FP32_FP64 in the low byte, optionally
 // with one of HYDRO_SPEEDS_EINFELDT, HYDRO_SPEEDS_PVRS and one of
 // HYDRO_RECON_CONSERVED, HYDRO_RECON_CHARACTERISTIC; or HYDRO_FP64 with
@@ -441,9 +483,9 @@ int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : (p & HYDRO_RE
 int eos_of(int32_t p) { return (p & HYDRO_EOS_GAS_RADIATION) ? 1 : 0; }
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
-                             hipStream_t s, const StageArgs &a) {
+                             hipStream_t s, const StageArgs &a, int occ = 0) {
   hipError_t e = hyd::launch_stage(m->ndim, is_mixed(prec), stage, wl.kmask, speeds_of(prec), recon_of(prec),
-                                   eos_of(prec), grid_of(wl, grid), s, a);
+                                   eos_of(prec), grid_of(wl, grid), s, a, occ);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("stage launch: ") + hipGetErrorString(e));
   return HYDRO_OK;
 }
@@ -461,10 +503,26 @@ hydro_status nonphys(const DevTime &h) {
 
 hydro_status rebuild_batch_items(hydro_batch *b) {
   std::vector<WorkItem> items;
+  std::vector<int32_t> fused;
   int kmask = 0;
-  build_items(b->m, b->ids, b->cfg, items, kmask);
+  build_items(b->m, b->ids, b->cfg, items, kmask, &fused);
   hydro_status st = upload_items(items, kmask, b->wl, b->m->stream);
   if (st) return st;
+  int32_t *d = nullptr;
+  if (!fused.empty()) {
+    if (hipMalloc(&d, fused.size() * sizeof(int32_t)) != hipSuccess)
+      return fail(HYDRO_ENOMEM, "fused block list: hipMalloc failed");
+    hipError_t e = hipMemcpyAsync(d, fused.data(), fused.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  b->m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->m->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(HYDRO_EDEVICE, std::string("fused block list upload: ") + hipGetErrorString(e));
+    }
+  }
+  if (b->d_fused) (void)hipFree(b->d_fused);
+  b->d_fused = d;
+  b->nfused = (int)fused.size();
   // the captured graph holds the old work list
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -657,6 +715,7 @@ hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, 
     st = fail(HYDRO_EDEVICE, "batch: stream creation failed");
   if (st) {
     if (bt->wl.d_items) (void)hipFree(bt->wl.d_items);
+    if (bt->d_fused) (void)hipFree(bt->d_fused);
     if (bt->d_time) (void)hipFree(bt->d_time);
     delete bt;
     return st;
@@ -674,6 +733,7 @@ hydro_status hydro_batch_destroy(hydro_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   (void)hipFree(b->wl.d_items);
+  if (b->d_fused) (void)hipFree(b->d_fused);
   (void)hipFree(b->d_time);
   for (auto *p : b->packets) p->batches--;
   b->m->children--;
@@ -709,11 +769,15 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   b->graph = nullptr;
   const int prec = b->prec;
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  hydro_status st =
-      launch_stage_wl(m, prec, 1, b->wl, b->grid, b->cap_stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+  hydro_status st = launch_stage_wl(m, prec, 1, b->wl, b->grid, b->cap_stream,
+                                    stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
   if (!st)
     st = launch_stage_wl(m, prec, 2, b->wl, b->grid, b->cap_stream,
-                         stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+                         stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
+  if (!st && hyd::launch_fused(is_mixed(prec), b->nfused, b->cap_stream,
+                               fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
+                                          b->remap)) != hipSuccess)
+    st = fail(HYDRO_EDEVICE, "fused step launch failed");
   if (!st && hyd::launch_finalize(b->d_time, cfl, 0, b->cap_stream) != hipSuccess)
     st = fail(HYDRO_EDEVICE, "finalize launch failed");
   hipGraph_t g = nullptr;
@@ -755,6 +819,9 @@ static hydro_status batch_run(hydro_batch *b, int32_t nsteps, double cfl, double
   if (e == hipSuccess)
     e = hyd::launch_lambda(m->ndim, is_mixed(b->prec), b->wl.kmask, eos_of(b->prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
+  if (e == hipSuccess)
+    e = hyd::launch_fused(is_mixed(b->prec), b->nfused, m->stream,
+                          fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, nullptr, b->d_time, gamma, 1, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
   std::vector<hipEvent_t> ev(step_ms ? nsteps + 1 : 0, nullptr);
@@ -807,6 +874,9 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   if (e == hipSuccess)
     e = hyd::launch_lambda(m->ndim, is_mixed(prec), b->wl.kmask, eos_of(prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
+  if (e == hipSuccess)
+    e = hyd::launch_fused(is_mixed(prec), b->nfused, m->stream,
+                          fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, nullptr, b->d_time, gamma, 1, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
   std::vector<hipEvent_t> ev(3 * nsteps + 1, nullptr);
@@ -814,10 +884,16 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
   hydro_status st = HYDRO_OK;
   HIP_TRY(hipEventRecord(ev[0], m->stream));
   for (int s = 0; s < nsteps && !st; ++s) {
-    st = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+    st = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream,
+                         stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
     if (!st && hipEventRecord(ev[3 * s + 1], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st)
-      st = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream, stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap));
+      st = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream,
+                           stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
+    if (!st && hyd::launch_fused(is_mixed(prec), b->nfused, m->stream,
+                                 fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
+                                            b->remap)) != hipSuccess)
+      st = fail(HYDRO_EDEVICE, "fused step launch failed");
     if (!st && hipEventRecord(ev[3 * s + 2], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
     if (!st && hyd::launch_finalize(b->d_time, cfl, 0, m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "finalize");
     if (!st && hipEventRecord(ev[3 * s + 3], m->stream) != hipSuccess) st = fail(HYDRO_EDEVICE, "event record");
@@ -870,6 +946,13 @@ struct hydro_stream {
   hipStream_t ctl = nullptr;
   hipEvent_t ready = nullptr;
   DevTime *d_time = nullptr;
+  // CPU/GPU split: the last cpu_packets packets are advanced by host threads
+  int cpu_packets = 0;
+  int cpu_threads = 1;
+  std::vector<double> cpu_u1;  // first-stage state of the CPU packets (host)
+  std::vector<int32_t> cpu_ids;
+  std::vector<double *> cpu_un;        // per block (global id): Un in the host arena
+  std::vector<double *> cpu_u1p;       // per block: its first-stage state in cpu_u1
 };
 
 namespace {
@@ -889,6 +972,19 @@ void stream_free(hydro_stream *s) {
   if (s->d_blocks) (void)hipFree(s->d_blocks);
   if (s->d_time) (void)hipFree(s->d_time);
   delete s;
+}
+
+// Packets of uneven size: each packet the GPU takes goes to the slot with the
+// fewest bytes so far, so the slot streams finish a step together.
+void assign_slots(hydro_stream *s) {
+  const int ngpu = (int)s->wl.size() - s->cpu_packets;
+  std::vector<int64_t> load(s->slots.size(), 0);
+  s->pslot.assign(s->wl.size(), -1);
+  for (int p = 0; p < ngpu; ++p) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    s->pslot[p] = k;
+    load[k] += s->plen[p];
+  }
 }
 
 StageArgs slot_args(const hydro_stream *s, const hydro_stream::Slot &sl, const WorkList &wl, int stage, double gamma) {
@@ -989,15 +1085,7 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
     if (upload_items(items, kmask, s->wl[p], s->ctl)) return bail(HYDRO_ENOMEM, "stream: work list upload failed");
   }
   s->slots.resize(nslots);
-  // packets of uneven size: each goes to the slot with the fewest bytes so far,
-  // so the slot streams finish a step together
-  std::vector<int64_t> load(nslots, 0);
-  s->pslot.resize(npackets);
-  for (int p = 0; p < npackets; ++p) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    s->pslot[p] = k;
-    load[k] += plen[p];
-  }
+  assign_slots(s);
   for (auto &sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
@@ -1022,12 +1110,14 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   const int np = (int)s->wl.size();
+  const int ngpu = np - s->cpu_packets;  // packets [ngpu, np) run on the host
+  const bool split = s->cpu_packets > 0;
   const int prec = s->prec;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   bool good = true;
   const int ns = (int)s->slots.size();
   std::vector<int> lastp(ns, -1);  // last packet of each slot
-  for (int p = 0; p < np; ++p) lastp[s->pslot[p]] = p;
+  for (int p = 0; p < ngpu; ++p) lastp[s->pslot[p]] = p;
   // every slot stream starts after the control stream's last work
   auto fan_out = [&]() {
     good = good && ok(hipEventRecord(s->ready, s->ctl));
@@ -1041,25 +1131,46 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
     good = good && ok(hipMemcpyAsync(sl.state, s->host + s->phost[p], (size_t)s->plen[p] * sizeof(double),
                                      hipMemcpyHostToDevice, sl.stream));
   };
+  // the host share: its CFL rate and non-physical flag go into the device
+  // accumulator on the control stream, ahead of the dt update
+  auto fold = [&](const hyd::HostRate &r) {
+    good = good && ok(hyd::launch_fold(s->d_time, r.lam, r.bad, r.bad_block, s->ctl));
+  };
+  hyd::HostStage H;
+  H.desc = s->desc.data();
+  H.ndim = s->ndim;
+  H.ids = s->cpu_ids;
+  H.gamma = gamma;
   // dt of the first step: rate of every packet's current state
   good = good && ok(hyd::launch_reset(s->d_time, s->ctl));
   fan_out();
-  for (int p = 0; p < np && good; ++p) {
+  for (int p = 0; p < ngpu && good; ++p) {
     auto &sl = s->slots[s->pslot[p]];
     copy_in(p, sl);
     good = good && ok(hyd::launch_lambda(s->ndim, is_mixed(prec), s->wl[p].kmask, eos_of(prec), s->wl[p].nitems, sl.stream,
                                          slot_args(s, sl, s->wl[p], 1, gamma)));
     if (p == lastp[s->pslot[p]]) done(sl);
   }
+  if (split && good) {
+    H.src = s->cpu_un.data();
+    fold(hyd::host_run(H, s->cpu_threads, true));
+  }
   good = good && ok(hyd::launch_finalize(s->d_time, cfl, 1, s->ctl));
   good = good && ok(hipEventRecord(s->ready, s->ctl));
   // Each step: a slot copies its first packet in before it waits for the new
   // dt (the copies of one step's tail and the next step's head overlap the
   // dt update); the control stream waits for every slot's last stage-2 launch
-  // (not its copy-out) before it computes the next dt.
+  // (not its copy-out) before it computes the next dt.  With a host share the
+  // host reads dt first (it computes with it), then queues the GPU packets,
+  // advances its own packets while they run, and folds its rate in.
   for (int step = 0; step < nsteps && good; ++step) {
+    DevTime h;
+    if (split) {
+      good = ok(hipMemcpyAsync(&h, s->d_time, sizeof(DevTime), hipMemcpyDeviceToHost, s->ctl)) &&
+             ok(hipStreamSynchronize(s->ctl));
+    }
     std::vector<char> waited(ns, 0);
-    for (int p = 0; p < np && good; ++p) {
+    for (int p = 0; p < ngpu && good; ++p) {
       const int k = s->pslot[p];
       auto &sl = s->slots[k];
       copy_in(p, sl);
@@ -1074,6 +1185,21 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
       if (p == lastp[k]) done(sl);
       good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
                                        hipMemcpyDeviceToHost, sl.stream));
+    }
+    // a failed earlier step leaves dt NaN: the host share then does nothing either
+    if (split && good && std::fabs(h.dt) <= DBL_MAX) {
+      H.dt = h.dt;
+      H.stage = 1;
+      H.src = s->cpu_un.data();
+      H.un = nullptr;
+      H.dst = s->cpu_u1p.data();
+      hyd::HostRate r = hyd::host_run(H, s->cpu_threads, false);
+      H.stage = 2;
+      H.src = s->cpu_u1p.data();
+      H.un = s->cpu_un.data();
+      H.dst = s->cpu_un.data();  // Un+1 over Un: stage 2 reads Un only at the cell it writes
+      r = hyd::host_run(H, s->cpu_threads, false);
+      fold(r);
     }
     good = good && ok(hyd::launch_finalize(s->d_time, cfl, 0, s->ctl));
     good = good && ok(hipEventRecord(s->ready, s->ctl));
@@ -1091,6 +1217,41 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   return HYDRO_OK;
 }
 
+hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, int32_t nthreads) {
+  if (!s) return fail(HYDRO_EINVAL, "stream is null");
+  const int np = (int)s->wl.size();
+  if (cpu_packets < 0 || cpu_packets > np) return fail(HYDRO_EINVAL, "cpu_packets must be in 0..npackets");
+  if (nthreads < 0) return fail(HYDRO_EINVAL, "nthreads must be >= 0");
+  if (cpu_packets > 0 && s->prec != HYDRO_FP64 && s->prec != HYDRO_FP32_FP64)
+    return fail(HYDRO_EINVAL, "the host share runs Davis bounds, primitive PLM and the gamma law only");
+  const int nb = (int)s->desc.size();
+  int64_t len = 0;
+  for (int p = np - cpu_packets; p < np; ++p) len += s->plen[p];
+  std::vector<double> u1;
+  try {
+    u1.resize((size_t)len);
+  } catch (...) {
+    return fail(HYDRO_ENOMEM, "host first-stage buffer allocation failed");
+  }
+  s->cpu_u1.swap(u1);
+  s->cpu_un.assign(nb, nullptr);
+  s->cpu_u1p.assign(nb, nullptr);
+  s->cpu_ids.clear();
+  int64_t base = 0;
+  for (int p = np - cpu_packets; p < np; ++p) {
+    for (int b = s->pstart[p]; b < s->pstart[p + 1]; ++b) {
+      s->cpu_ids.push_back(b);
+      s->cpu_un[b] = s->host + s->desc[b].offset;
+      s->cpu_u1p[b] = s->cpu_u1.data() + base + (s->desc[b].offset - s->phost[p]);
+    }
+    base += s->plen[p];
+  }
+  s->cpu_packets = cpu_packets;
+  s->cpu_threads = nthreads > 0 ? nthreads : std::max(1u, std::thread::hardware_concurrency());
+  assign_slots(s);
+  return HYDRO_OK;
+}
+
 }  // extern "C"
 
 extern "C" {
@@ -1098,9 +1259,19 @@ extern "C" {
 // ------------------------------------------------------------------ tuning
 hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, int32_t zchunk) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
-  if (tile < 0 || tile > 4) return fail(HYDRO_EINVAL, "tile must be 0 (16x16), 1 (8x8) or 2..4 (16x16 z-runs)");
+  if (tile < 0 || tile > TILE_FUSED)
+    return fail(HYDRO_EINVAL, "tile must be 0 (16x16), 1 (8x8), 2..4 (16x16 z-runs) or 5 (fused step)");
   if (zchunk < 0) return fail(HYDRO_EINVAL, "zchunk must be >= 0");
-  if (tile != 1 && edge > 0 && edge % 16) return fail(HYDRO_EINVAL, "16x16 tiles need an edge multiple of 16");
+  if (tile == TILE_FUSED) {
+    if (edge != 8 || zchunk != 0) return fail(HYDRO_EINVAL, "the fused step takes whole 8^3 blocks (edge 8, zchunk 0)");
+    if (is_mixed(b->prec) ? b->prec != HYDRO_FP32_FP64 : b->prec != HYDRO_FP64)
+      return fail(HYDRO_EINVAL, "the fused step runs Davis bounds, primitive PLM and the gamma law only");
+    for (int id : b->ids)
+      if (block_class(b->m->desc[id], b->m->ndim) == 8 && !fusable(b->m->desc[id], b->m->ndim))
+        return fail(HYDRO_EINVAL, "the fused step needs every block of the class periodic on itself (3D, 8^3)");
+  }
+  if (tile != 1 && tile != TILE_FUSED && edge > 0 && edge % 16)
+    return fail(HYDRO_EINVAL, "16x16 tiles need an edge multiple of 16");
   if (tile >= 2 && zchunk != 0) return fail(HYDRO_EINVAL, "z-runs take whole blocks (zchunk 0)");
   TileCfg c;
   c.tile = tile;
@@ -1124,6 +1295,21 @@ hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_re
   return HYDRO_OK;
 }
 
+hydro_status hydro_batch_set_occupancy(hydro_batch *b, int32_t waves) {
+  if (!b) return fail(HYDRO_EINVAL, "batch is null");
+  if (waves != 0 && (waves < 2 || waves > 4)) return fail(HYDRO_EINVAL, "waves must be 0 (default) or 2..4");
+  if (waves != 0 && b->prec != HYDRO_FP64 && b->prec != HYDRO_FP32_FP64)
+    return fail(HYDRO_EINVAL, "an occupancy request applies to the default method only");
+  if (waves != b->occ) {
+    b->occ = waves;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+  }
+  return HYDRO_OK;
+}
+
 hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass_max, int32_t *nclass) {
   if (!b || !out || !nclass || nclass_max < 0) return fail(HYDRO_EINVAL, "bad arguments");
   std::map<int, int64_t> cells, tiles;
@@ -1134,6 +1320,7 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
   }
   out[0] = b->grid;
   out[1] = b->remap;
+  out[2] = b->occ;
   int k = 0;
   for (auto &kv : cells) {
     if (k < nclass_max) {
@@ -1147,17 +1334,19 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
           break;
         }
       const bool can16 = any && any->n[0] % 16 == 0 && any->n[1] % 16 == 0;
-      out[2 + 4 * k + 0] = kv.first;
-      // the tiling in effect: 8x8, 16x16, or the z-run length
+      out[3 + 4 * k + 0] = kv.first;
+      // the tiling in effect: 8x8, 16x16, the z-run length, or the fused step
       int tile = 1;
-      if (can16 && c.tile != 1) {
+      if (c.tile == TILE_FUSED) {
+        tile = TILE_FUSED;
+      } else if (can16 && c.tile != 1) {
         const bool whole = b->m->ndim == 3 && (c.zchunk == 0 || (any && c.zchunk >= any->n[2]));
         const int run = !whole ? 1 : (c.tile < 0 ? default_run(b->m, tiles[kv.first]) : std::max(c.tile, 1));
         tile = run > 1 ? run : 0;
       }
-      out[2 + 4 * k + 1] = tile;
-      out[2 + 4 * k + 2] = c.zchunk;
-      out[2 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
+      out[3 + 4 * k + 1] = tile;
+      out[3 + 4 * k + 2] = c.zchunk;
+      out[3 + 4 * k + 3] = (int32_t)(kv.second & 0x7fffffff);
     }
     ++k;
   }
@@ -1175,7 +1364,7 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
 // timed because a tiling can shift work between them (stage 2 carries Un
 // and the CFL rate).
 static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int remap, double gamma, int reps,
-                              double &ms) {
+                              double &ms, int occ = 0) {
   hydro_mesh *m = b->m;
   const int prec = b->prec;
   hipEvent_t e0, e1;
@@ -1192,10 +1381,10 @@ static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int 
   for (int stage = 1; stage <= 2 && !st; ++stage) {
     const StageArgs &a = args[stage - 1];
     std::vector<double> t;
-    st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a);  // warm-up
+    st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a, occ);  // warm-up
     for (int r = 0; r < reps && !st; ++r) {
       (void)hipEventRecord(e0, m->stream);
-      st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a);
+      st = launch_stage_wl(m, prec, stage, wl, grid, m->stream, a, occ);
       (void)hipEventRecord(e1, m->stream);
       if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
       float f = 0;
@@ -1219,7 +1408,8 @@ static hydro_status time_step(hydro_batch *b, const WorkList &wl, int grid, int 
 // stage-2 code path -- z-run marching, the Un stream, the rate epilogue -- is
 // compared on the sample alone).
 static hydro_status stage_sample(hydro_batch *b, int stage, const std::vector<int32_t> &ids,
-                                 const std::map<int, TileCfg> &cfg, double gamma, std::vector<double> &out) {
+                                 const std::map<int, TileCfg> &cfg, double gamma, std::vector<double> &out,
+                                 int occ = 0) {
   hydro_mesh *m = b->m;
   std::vector<WorkItem> items;
   int kmask;
@@ -1231,7 +1421,7 @@ static hydro_status stage_sample(hydro_batch *b, int stage, const std::vector<in
   a.src = m->arena;
   a.un = m->arena;
   a.dst = m->u1;
-  st = launch_stage_wl(m, b->prec, stage, wl, 0, m->stream, a);
+  st = launch_stage_wl(m, b->prec, stage, wl, 0, m->stream, a, occ);
   out.clear();
   for (int id : ids) {
     if (st) break;
@@ -1248,12 +1438,153 @@ static hydro_status stage_sample(hydro_batch *b, int stage, const std::vector<in
   return st;
 }
 
+// Device buffer freed on scope exit (tuning temporaries).
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes > 0 ? bytes : 1); }
+};
+
+// One SSP-RK2 step (dt 1e-3) of the listed self-periodic blocks, copied into
+// a compact temporary arena: with the two stage kernels of the default tiling
+// (fused = false) or with the fused kernel.  `out` receives the result in the
+// compact layout.  The caller's arena and the mesh's scratch are not written.
+static hydro_status fused_sample_step(hydro_batch *b, const std::vector<int32_t> &ids, bool fused, double gamma,
+                                      std::vector<double> &out) {
+  hydro_mesh *m = b->m;
+  const int n = (int)ids.size();
+  std::vector<hydro_block_desc> local(n);
+  int64_t len = 0;
+  for (int i = 0; i < n; ++i) {
+    local[i] = m->desc[ids[i]];
+    local[i].offset = len;
+    len += 5 * (int64_t)local[i].n[0] * local[i].n[1] * local[i].n[2];
+  }
+  std::vector<DevBlock> hb(n);
+  for (int i = 0; i < n; ++i) hb[i] = make_devblock(local.data(), i, m->ndim);
+  hydro_mesh view;
+  view.ndim = m->ndim;
+  view.nblocks = n;
+  view.desc = local;
+  view.num_cu = m->num_cu;
+  std::vector<int32_t> lid(n);
+  for (int i = 0; i < n; ++i) lid[i] = i;
+  std::vector<WorkItem> items;
+  int kmask = 0;
+  build_items(&view, lid, {}, items, kmask);
+  DevBuf state, u1, blocks, its, dids, tm;
+  if (state.alloc(len * sizeof(double)) || u1.alloc(len * sizeof(double)) || blocks.alloc(n * sizeof(DevBlock)) ||
+      its.alloc(items.size() * sizeof(WorkItem)) || dids.alloc(n * sizeof(int32_t)) || tm.alloc(sizeof(DevTime)))
+    return fail(HYDRO_ENOMEM, "tuning: hipMalloc of the fused-step sample failed");
+  hipStream_t s = m->stream;
+  HIP_TRY(hipMemcpyAsync(blocks.p, hb.data(), n * sizeof(DevBlock), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(its.p, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dids.p, lid.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hyd::launch_reset(static_cast<DevTime *>(tm.p), s));
+  double *st = static_cast<double *>(state.p);
+  for (int i = 0; i < n; ++i)
+    HIP_TRY(hipMemcpyAsync(st + local[i].offset, m->arena + m->desc[ids[i]].offset,
+                           5 * (size_t)local[i].n[0] * local[i].n[1] * local[i].n[2] * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  const double dt = 1e-3;
+  const bool mixed = is_mixed(b->prec);
+  if (fused) {
+    hyd::FusedArgs a;
+    a.blocks = static_cast<DevBlock *>(blocks.p);
+    a.ids = static_cast<int32_t *>(dids.p);
+    a.nblocks = n;
+    a.rate_only = 0;
+    a.xcd_remap = 1;
+    a.state = st;
+    a.dt = dt;
+    a.dt_dev = nullptr;
+    a.acc = static_cast<DevTime *>(tm.p);
+    a.gamma = gamma;
+    HIP_TRY(hyd::launch_fused(mixed, n, s, a));
+  } else {
+    StageArgs a;
+    a.blocks = static_cast<DevBlock *>(blocks.p);
+    a.items = static_cast<WorkItem *>(its.p);
+    a.nitems = (int)items.size();
+    a.reset_time = 1;
+    a.xcd_remap = 1;
+    a.src = st;
+    a.un = st;
+    a.dst = static_cast<double *>(u1.p);
+    a.dt = dt;
+    a.dt_dev = nullptr;
+    a.acc = static_cast<DevTime *>(tm.p);
+    a.gamma = gamma;
+    HIP_TRY(hyd::launch_stage(m->ndim, mixed, 1, kmask, 0, 0, 0, a.nitems, s, a));
+    a.reset_time = 0;
+    a.src = static_cast<double *>(u1.p);
+    a.dst = st;
+    HIP_TRY(hyd::launch_stage(m->ndim, mixed, 2, kmask, 0, 0, 0, a.nitems, s, a));
+  }
+  out.resize(len);
+  HIP_TRY(hipMemcpyAsync(out.data(), st, len * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return HYDRO_OK;
+}
+
+// Median device time (ms) of `reps` whole steps of the batch as configured:
+// the stage-1 and stage-2 launches over its work list and the fused launch
+// of its fused classes, on a copy of the state in the mesh's scratch buffer
+// (stage 1 from the arena into the scratch; stage 2 with the arena as
+// stencil and the scratch as Un and output; the fused step in place in the
+// scratch), so the caller's arena is not written.
+static hydro_status time_full(hydro_batch *b, double gamma, int reps, double &ms) {
+  hydro_mesh *m = b->m;
+  const int prec = b->prec;
+  HIP_TRY(hipMemcpyAsync(m->u1, m->arena, (size_t)m->arena_len * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  const double dt = 1e-30;
+  StageArgs a1 = stage_args(m, b->wl, 1, dt, nullptr, b->d_time, gamma, 0, b->remap);
+  StageArgs a2 = stage_args(m, b->wl, 2, dt, nullptr, b->d_time, gamma, 0, b->remap);
+  a2.src = m->arena;
+  a2.un = m->u1;
+  a2.dst = m->u1;
+  const hyd::FusedArgs af = fused_args(m, b->d_fused, b->nfused, m->u1, dt, nullptr, b->d_time, gamma, 0, b->remap);
+  auto step = [&]() -> hydro_status {
+    hydro_status s2 = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, a1, b->occ);
+    if (!s2) s2 = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream, a2, b->occ);
+    if (!s2 && hyd::launch_fused(is_mixed(prec), b->nfused, m->stream, af) != hipSuccess)
+      s2 = fail(HYDRO_EDEVICE, "tuning: fused launch failed");
+    return s2;
+  };
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HYDRO_EDEVICE, "tuning: event create failed");
+  }
+  hydro_status st = step();  // warm-up
+  std::vector<double> t;
+  for (int r = 0; r < reps && !st; ++r) {
+    (void)hipEventRecord(e0, m->stream);
+    st = step();
+    (void)hipEventRecord(e1, m->stream);
+    if (!st && hipEventSynchronize(e1) != hipSuccess) st = fail(HYDRO_EDEVICE, "tuning: event sync failed");
+    float f = 0;
+    (void)hipEventElapsedTime(&f, e0, e1);
+    t.push_back(f);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  std::sort(t.begin(), t.end());
+  ms = t[t.size() / 2];
+  return HYDRO_OK;
+}
+
 hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
   if (reps < 1) return fail(HYDRO_EINVAL, "reps must be >= 1");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
   hydro_mesh *m = b->m;
   const double tol = is_mixed(b->prec) ? 1e-6 : 1e-13;
+  std::vector<int> fused_ok;  // classes whose fused step passed the parity check
   std::map<int, std::vector<int32_t>> cls;
   for (int id : b->ids) cls[block_class(m->desc[id], m->ndim)].push_back(id);
   for (auto &kv : cls) {
@@ -1320,6 +1651,23 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
         bestc = c;
       }
     }
+    // the fused step of self-periodic 8^3 blocks: both stages in one launch,
+    // kept when it passes the same parity check (one full step on the sample
+    // against the default two-launch step) and beats the best tiling's two
+    // stage launches
+    bool all_fusable = edge == 8 && (b->prec == HYDRO_FP64 || b->prec == HYDRO_FP32_FP64);
+    for (int id : ids) all_fusable = all_fusable && fusable(m->desc[id], m->ndim);
+    if (all_fusable) {
+      std::vector<double> r2, g2;
+      st = fused_sample_step(b, sample, false, gamma, r2);
+      if (!st) st = fused_sample_step(b, sample, true, gamma, g2);
+      if (st) return st;
+      bool ok = r2.size() == g2.size();
+      double scale = 0.0;
+      for (double x : r2) scale = std::max(scale, std::fabs(x));
+      for (size_t i = 0; ok && i < r2.size(); ++i) ok = std::fabs(g2[i] - r2[i]) <= tol * (std::fabs(r2[i]) + 1e-6 * scale);
+      if (ok) fused_ok.push_back(edge);  // decided on the whole step below
+    }
     b->cfg[edge] = bestc;
   }
   hydro_status st = rebuild_batch_items(b);
@@ -1340,7 +1688,63 @@ hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
         bestr = r;
       }
     }
-  return hydro_batch_set_launch(b, bestg, bestr);
+  st = hydro_batch_set_launch(b, bestg, bestr);
+  if (st) return st;
+  // the fused step of a class, kept when the whole step (stage launches of
+  // the other classes plus the fused launch) is faster with it: the class's
+  // share of the stage launches and the separate launch interact, so the
+  // class's own times do not decide it
+  for (int edge : fused_ok) {
+    const TileCfg keep = b->cfg[edge];
+    double t_keep = 0, t_fused = 0;
+    st = time_full(b, gamma, reps, t_keep);
+    if (st) return st;
+    TileCfg f;
+    f.tile = TILE_FUSED;
+    b->cfg[edge] = f;
+    st = rebuild_batch_items(b);
+    if (!st) st = time_full(b, gamma, reps, t_fused);
+    if (st) return st;
+    if (!(t_fused < t_keep)) {
+      b->cfg[edge] = keep;
+      st = rebuild_batch_items(b);
+      if (st) return st;
+    }
+  }
+  // occupancy: the register budget of 2, 3 or 4 waves per SIMD against the
+  // kernels' own (default method only), each parity-checked on the sample of
+  // every class against the default budget
+  int besto = 0;
+  if (b->prec == HYDRO_FP64 || b->prec == HYDRO_FP32_FP64) {
+    std::vector<int32_t> sample;
+    for (auto &kv : cls)
+      sample.insert(sample.end(), kv.second.begin(), kv.second.begin() + std::min<size_t>(kv.second.size(), 16));
+    std::vector<double> ref[2], got;
+    for (int stage = 1; stage <= 2 && !st; ++stage) st = stage_sample(b, stage, sample, b->cfg, gamma, ref[stage - 1]);
+    if (st) return st;
+    for (int o : {2, 3, 4}) {
+      bool ok = true;
+      for (int stage = 1; stage <= 2 && ok; ++stage) {
+        st = stage_sample(b, stage, sample, b->cfg, gamma, got, o);
+        if (st) return st;
+        const std::vector<double> &rr = ref[stage - 1];
+        ok = got.size() == rr.size();
+        double scale = 0.0;
+        for (double x : rr) scale = std::max(scale, std::fabs(x));
+        for (size_t i = 0; ok && i < rr.size(); ++i)
+          ok = std::fabs(got[i] - rr[i]) <= tol * (std::fabs(rr[i]) + 1e-6 * scale);
+      }
+      if (!ok) continue;
+      double ms = 0;
+      st = time_step(b, b->wl, bestg, bestr, gamma, reps, ms, o);
+      if (st) return st;
+      if (ms < best) {
+        best = ms;
+        besto = o;
+      }
+    }
+  }
+  return hydro_batch_set_occupancy(b, besto);
 }
 
 }  // extern "C"

@@ -66,15 +66,34 @@ struct StageArgs {
   double gamma;
 };
 
+// Arguments of the fused step of self-periodic 8^3 blocks (one workgroup per
+// listed block; Un+1 overwrites Un in place).
+struct FusedArgs {
+  const DevBlock *blocks;
+  const int32_t *ids;  // the blocks the fused kernel takes
+  int32_t nblocks;
+  int32_t rate_only;   // 1: only reduce the CFL rate of the current state into acc
+  int32_t xcd_remap;
+  double *state;
+  double dt;           // used when dt_dev is null
+  const DevTime *dt_dev;
+  DevTime *acc;
+  double gamma;
+};
+
 // kmask: bit 0 = the launch contains 16x16 items, bit 1 = 8x8 items.
 // speeds: 0 = Davis, 1 = Einfeldt, 2 = pressure-based (PVRS) wave-speed bounds in HLLC.
 // recon: 0 = PLM on primitives, 1 = on conserved variables, 2 = on characteristic variables.
 // eos: 0 = gamma law, 1 = gas + radiation (FP64 with Davis bounds and primitive PLM only).
+// occ: 0 = the kernels' own register budget; 2, 3 or 4 = at least that many
+// waves per SIMD (default method only; the variants keep their own).
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int eos, int grid,
-                        hipStream_t s, const StageArgs &a);
+                        hipStream_t s, const StageArgs &a, int occ = 0);
 // mixed: the rate as the mixed path's stage 2 reduces it (refined hardware
 // reciprocal and reciprocal square root); else in oracle order.
 hipError_t launch_lambda(int ndim, bool mixed, int kmask, int eos, int grid, hipStream_t s, const StageArgs &a);
+hipError_t launch_fused(bool mixed, int grid, hipStream_t s, const FusedArgs &a);
+hipError_t launch_fold(DevTime *t, double lam, int bad, int bad_block, hipStream_t s);
 hipError_t launch_reset(DevTime *t, hipStream_t s);
 hipError_t launch_finalize(DevTime *t, double cfl, int init, hipStream_t s);
 

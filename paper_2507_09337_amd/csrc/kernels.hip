@@ -8,8 +8,8 @@ namespace hyd {
 
 // Stage launchers of the instantiation units, one per (dimension, mixed, stage).
 #define HYD_DECL(D, M, S)                                                                                     \
-  hipError_t launch_stage_inst_##D##_##M##_##S(int kmask, int speeds, int recon, int eos, int grid, hipStream_t s, \
-                                               const StageArgs &a);
+  hipError_t launch_stage_inst_##D##_##M##_##S(int kmask, int speeds, int recon, int eos, int occ, int grid,      \
+                                               hipStream_t s, const StageArgs &a);
 HYD_DECL(2, 0, 1)
 HYD_DECL(2, 0, 2)
 HYD_DECL(2, 1, 1)
@@ -50,17 +50,20 @@ __global__ void k_finalize(DevTime *t, double cfl, int init) {
 // Launchers.
 // ------------------------------------------------------------------------
 hipError_t launch_stage(int ndim, bool mixed, int stage, int kmask, int speeds, int recon, int eos, int grid,
-                        hipStream_t s, const StageArgs &a) {
+                        hipStream_t s, const StageArgs &a, int occ) {
   if (grid <= 0) return hipSuccess;
   if (eos == EOS_GAS_RADIATION && (mixed || speeds != SPEEDS_DAVIS || recon != RECON_PRIMITIVE))
     return hipErrorInvalidValue;  // FP64, Davis bounds, primitive PLM only (checked by the caller)
-  const int k = kmask, w = speeds, r = recon, e = eos;
+  if (occ != 0 && (occ < 2 || occ > 4)) return hipErrorInvalidValue;
+  const int k = kmask, w = speeds, r = recon, e = eos, o = occ;
   if (ndim == 2) {
-    if (mixed) return stage == 1 ? launch_stage_inst_2_1_1(k, w, r, e, grid, s, a) : launch_stage_inst_2_1_2(k, w, r, e, grid, s, a);
-    return stage == 1 ? launch_stage_inst_2_0_1(k, w, r, e, grid, s, a) : launch_stage_inst_2_0_2(k, w, r, e, grid, s, a);
+    if (mixed)
+      return stage == 1 ? launch_stage_inst_2_1_1(k, w, r, e, o, grid, s, a) : launch_stage_inst_2_1_2(k, w, r, e, o, grid, s, a);
+    return stage == 1 ? launch_stage_inst_2_0_1(k, w, r, e, o, grid, s, a) : launch_stage_inst_2_0_2(k, w, r, e, o, grid, s, a);
   }
-  if (mixed) return stage == 1 ? launch_stage_inst_3_1_1(k, w, r, e, grid, s, a) : launch_stage_inst_3_1_2(k, w, r, e, grid, s, a);
-  return stage == 1 ? launch_stage_inst_3_0_1(k, w, r, e, grid, s, a) : launch_stage_inst_3_0_2(k, w, r, e, grid, s, a);
+  if (mixed)
+    return stage == 1 ? launch_stage_inst_3_1_1(k, w, r, e, o, grid, s, a) : launch_stage_inst_3_1_2(k, w, r, e, o, grid, s, a);
+  return stage == 1 ? launch_stage_inst_3_0_1(k, w, r, e, o, grid, s, a) : launch_stage_inst_3_0_2(k, w, r, e, o, grid, s, a);
 }
 
 template <int EOS, bool MIXED>
@@ -89,6 +92,30 @@ hipError_t launch_lambda(int ndim, bool mixed, int kmask, int eos, int grid, hip
   } else {
     launch_lambda_e<EOS_IDEAL, false>(ndim, t16, grid, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(bool mixed, int grid, hipStream_t s, const FusedArgs &a) {
+  if (grid <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL((k_fused_cube8<true>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_fused_cube8<false>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// The host share's CFL rate and non-physical flag, merged into the
+// accumulator (before the dt update of the step).
+__global__ void k_fold(DevTime *t, double lam, int bad, int bad_block) {
+  atomicMax(&t->lam_bits, (unsigned long long)__double_as_longlong(lam));
+  if (bad) {
+    atomicOr(&t->status, 1);
+    atomicMin(&t->bad_block, bad_block);
+  }
+}
+
+hipError_t launch_fold(DevTime *t, double lam, int bad, int bad_block, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(1), 0, s, t, lam, bad, bad_block);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 
 namespace hyd {
 
-hipError_t HYD_CAT(HYD_DIM, HYD_MIXED, HYD_STAGE)(int kmask, int speeds, int recon, int eos, int grid,
+hipError_t HYD_CAT(HYD_DIM, HYD_MIXED, HYD_STAGE)(int kmask, int speeds, int recon, int eos, int occ, int grid,
                                                    hipStream_t s, const StageArgs &a) {
   constexpr int D = HYD_DIM, S = HYD_STAGE;
   constexpr bool M = HYD_MIXED != 0;
@@ -24,6 +24,7 @@ hipError_t HYD_CAT(HYD_DIM, HYD_MIXED, HYD_STAGE)(int kmask, int speeds, int rec
       return launch_ks<D, false, S, SPEEDS_DAVIS, RECON_PRIMITIVE, EOS_GAS_RADIATION>(kmask, grid, s, a);
     }
   }
+  if (occ > 0 && speeds == SPEEDS_DAVIS && recon == RECON_PRIMITIVE) return launch_occ<D, M, S>(kmask, occ, grid, s, a);
   return launch_k<D, M, S>(kmask, speeds, recon, grid, s, a);
 }
 

@@ -70,13 +70,13 @@ struct Arith<float> {  // hardware reciprocal and reciprocal square root (about 
 // (a zero result may carry either sign, which no later sum or product can see
 // except in the sign of a zero).
 template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
+__host__ __device__ __forceinline__ T minmod(T a, T b) {
   return fmax(fmin(a, b), fmin(fmax(a, b), T(0)));
 }
 
 // PLM face states between w1 and w2 of four consecutive cells.
 template <typename T>
-__device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
+__host__ __device__ __forceinline__ void plm(T w0, T w1, T w2, T w3, T &l, T &r) {
   T d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
   l = w1 + T(0.5) * minmod(d01, d12);
   r = w2 - T(0.5) * minmod(d12, d23);
@@ -99,7 +99,7 @@ enum { EOS_IDEAL = 0, EOS_GAS_RADIATION = 1 };
 // so each result is rounded as in a CPU evaluation of the same formulas.
 constexpr double ARAD = 1.0;
 
-__device__ __forceinline__ double gr_temperature_e(double rho, double rhoe, double gamma) {
+__host__ __device__ __forceinline__ double gr_temperature_e(double rho, double rhoe, double gamma) {
 #pragma clang fp contract(off)
   const double cv = rho / (gamma - 1.0);
   double T = fmin(rhoe / cv, __builtin_sqrt(__builtin_sqrt(rhoe / ARAD)));
@@ -114,7 +114,7 @@ __device__ __forceinline__ double gr_temperature_e(double rho, double rhoe, doub
   return T;
 }
 
-__device__ __forceinline__ double gr_temperature_p(double rho, double p) {
+__host__ __device__ __forceinline__ double gr_temperature_p(double rho, double p) {
 #pragma clang fp contract(off)
   double T = fmin(p / rho, __builtin_sqrt(__builtin_sqrt(3.0 * p / ARAD)));
   for (int k = 0; k < 64; ++k) {
@@ -128,7 +128,7 @@ __device__ __forceinline__ double gr_temperature_p(double rho, double p) {
   return T;
 }
 
-__device__ __forceinline__ double gr_gamma1(double rho, double T, double p, double gamma) {
+__host__ __device__ __forceinline__ double gr_gamma1(double rho, double T, double p, double gamma) {
 #pragma clang fp contract(off)
   const double beta = rho * T / p;
   const double g1 = gamma - 1.0;
@@ -137,7 +137,7 @@ __device__ __forceinline__ double gr_gamma1(double rho, double T, double p, doub
 
 // Sound speed and internal energy per volume of a primitive state.
 template <int EOS>
-__device__ __forceinline__ void thermo_fp64(double r, double p, double g, double &c, double &e) {
+__host__ __device__ __forceinline__ void thermo_fp64(double r, double p, double g, double &c, double &e) {
 #pragma clang fp contract(off)
   if constexpr (EOS == EOS_GAS_RADIATION) {
     const double T = gr_temperature_p(r, p);
@@ -237,7 +237,7 @@ __device__ __forceinline__ void hllc(const float L[5], const float R[5], float g
 // device, so each face flux is rounded exactly as in a plain FP64 CPU
 // evaluation of the same formulas.  Only the side K of the contact is formed.
 template <int SPEEDS, int EOS = EOS_IDEAL>
-__device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], double g, double F[5]) {
+__host__ __device__ __forceinline__ void hllc_fp64(const double L[5], const double R[5], double g, double F[5]) {
 #pragma clang fp contract(off)
   const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
   const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
@@ -335,7 +335,7 @@ __device__ __forceinline__ bool state_ok(const double s[5]) {
 // FP64 primitive recovery (ideal gas), in the plain evaluation order
 // u = m/rho; rho e = E - (m_x u + m_y v + m_z w)/2; p = (gamma-1) rho e.
 // Returns false for rho <= 0, p <= 0 or non-finite values.
-__device__ __forceinline__ bool recover(double U0, double U1, double U2, double U3, double U4, double gm1,
+__host__ __device__ __forceinline__ bool recover(double U0, double U1, double U2, double U3, double U4, double gm1,
                                         double W[5]) {
 #pragma clang fp contract(off)
   const double u = U1 / U0, v = U2 / U0, w = U3 / U0;
@@ -411,7 +411,7 @@ __device__ __forceinline__ bool load_prim(const double *__restrict__ p, int64_t 
 
 // CFL rate of one cell, sum over active directions of (|u_d| + c)/dx_d.
 template <int DIM, int EOS = EOS_IDEAL>
-__device__ __forceinline__ double cell_rate(const double W[5], double gamma, double dx0, double dx1, double dx2) {
+__host__ __device__ __forceinline__ double cell_rate(const double W[5], double gamma, double dx0, double dx1, double dx2) {
 #pragma clang fp contract(off)
   double c, e;
   thermo_fp64<EOS>(W[0], W[4], gamma, c, e);
@@ -1375,9 +1375,11 @@ constexpr size_t stage_lds_bytes() {
 // registers, two waves) is held to three waves too: a few spilled dwords,
 // measured 4 % faster; its stage 2, and both stages of kernels that also
 // carry the 8x8 tile, spill too much at three and keep two.
-template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON, int EOS>
+// OCC > 0 asks instead for at least OCC waves per SIMD (the register budget
+// of OCC waves: 2, 3 or 4), a candidate of the autotuner.
+template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON, int EOS, int OCC = 0>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
-    (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1 && EOS == EOS_IDEAL)) ? 3 : 1)))
+    OCC > 0 ? OCC : (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1 && EOS == EOS_IDEAL)) ? 3 : 1)))
 void k_stage(StageArgs A) {
   static_assert(EOS == EOS_IDEAL || !MIXED, "the gas + radiation EOS runs on the FP64 tile only");
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
@@ -1431,6 +1433,198 @@ void k_stage(StageArgs A) {
   if (STAGE == 2) flush_acc(A.acc, lam, bad, badblk, true);
 }
 
+// ------------------------------------------------------------------------
+// Fused step of self-periodic 8^3 blocks: both RK stages of a block in one
+// workgroup, the block on chip.  The 512 cells' primitives of the current
+// stage source sit in LDS (each cell wraps around its own block, so the
+// stencil never leaves it); each of the 256 threads owns two cells and keeps
+// their Un and U1 in FP64 registers.  Per stage: recover the two cells into
+// LDS; barrier; the flux of the low x, y and z face of each owned cell (PLM +
+// HLLC from the four cells along the axis, wrapping) into three flux arrays;
+// barrier; dU = sum_d (dt/dx_d)(F_lo - F_hi) in x, y, z order.  Stage 2 writes
+// Un+1 over Un and reduces the CFL rate of the new state.  A workgroup loops
+// over its blocks and loads the next block's Un while it computes the
+// current one.  Un is read once and Un+1 written once: 80 algorithmic bytes
+// per cell-update instead of the two-launch step's 200 (no first-stage state
+// in HBM).  FP64: the oracle's operations in its order (bit-exact); MIXED:
+// the mixed tile's FP32 faces, FP64 recovery check, update and rate.  Davis
+// bounds, primitive PLM, gamma law.
+// rate_only = 1: only the CFL rate of the current state (the dt of a run's
+// first step).
+// ------------------------------------------------------------------------
+template <bool MIXED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 1))) void k_fused_cube8(FusedArgs A) {
+#pragma clang fp contract(off)
+  using T = typename std::conditional<MIXED, float, double>::type;
+  constexpr int N = 8, NC = N * N * N, NT = 256;
+  static_assert(2 * NT == NC, "two cells per thread");
+  __shared__ T W[NVAR * NC];
+  __shared__ T F[3][NVAR * NC];  // fluxes of the low x, y, z face of each cell
+  const double dt = A.rate_only ? 0.0 : (A.dt_dev ? A.dt_dev->dt : A.dt);
+  // a failed step (device dt not finite) leaves the state alone, as the stage kernels do
+  if (!A.rate_only && !(__builtin_fabs(dt) <= __DBL_MAX__)) return;
+  const double gamma = A.gamma, gm1 = gamma - 1.0;
+  const float g32 = (float)gamma, rgm1 = (float)(1.0 / gm1);
+  double lam = 0.0;
+  int bad = 0, badblk = INT_MAX;
+  const int tid = threadIdx.x;
+  auto recov = [&](const double (&U)[5], double (&Wd)[5]) {
+    return MIXED ? recover_fast(U[0], U[1], U[2], U[3], U[4], gm1, Wd)
+                 : recover(U[0], U[1], U[2], U[3], U[4], gm1, Wd);
+  };
+  auto rate = [&](const double (&Wd)[5], const DevBlock &B) {
+    return MIXED ? cell_rate_fast<3>(Wd, gamma, 1.0 / B.dx[0], 1.0 / B.dx[1], 1.0 / B.dx[2])
+                 : cell_rate<3>(Wd, gamma, B.dx[0], B.dx[1], B.dx[2]);
+  };
+  // low face of cell c along axis d: the four cells c - 2e_d .. c + e_d
+  // (wrapping around the block), rotated into the face frame (normal velocity
+  // first, the tangential ones in the order the other kernels use), HLLC, and
+  // the flux rotated back
+  auto face = [&](int c, int d) {
+    const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+    auto at = [&](int o) {
+      const int ii = d == 0 ? (i + o) & 7 : i, jj = d == 1 ? (j + o) & 7 : j, kk = d == 2 ? (k + o) & 7 : k;
+      return (kk * N + jj) * N + ii;
+    };
+    const int c0 = at(-2), c1 = at(-1), c3 = at(1);
+    T wl[5], wr[5];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      const T w0 = W[v * NC + c0], w1 = W[v * NC + c1], w2 = W[v * NC + c], w3 = W[v * NC + c3];
+      if constexpr (MIXED) {
+        const float d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
+        wl[v] = __builtin_fmaf(0.5f, minmod_f(d01, d12), w1);
+        wr[v] = __builtin_fmaf(-0.5f, minmod_f(d12, d23), w2);
+      } else {
+        plm(w0, w1, w2, w3, wl[v], wr[v]);
+      }
+    }
+    const int n = 1 + d, t1 = d == 1 ? 1 : 2, t2 = d == 2 ? 1 : 3;
+    const T L[5] = {wl[0], wl[n], wl[t1], wl[t2], wl[4]};
+    const T R[5] = {wr[0], wr[n], wr[t1], wr[t2], wr[4]};
+    T Fr[5];
+    if constexpr (MIXED)
+      hllc<SPEEDS_DAVIS>(L, R, g32, rgm1, Fr);
+    else
+      hllc_fp64<SPEEDS_DAVIS, EOS_IDEAL>(L, R, gamma, Fr);
+    T Fo[5];
+    Fo[0] = Fr[0];
+    Fo[4] = Fr[4];
+    Fo[n] = Fr[1];
+    Fo[t1] = Fr[2];
+    Fo[t2] = Fr[3];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) F[d][v * NC + c] = Fo[v];
+  };
+  // the cell above c along axis d (wrapping)
+  auto up = [&](int c, int d) {
+    const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+    return d == 0 ? (k * N + j) * N + ((i + 1) & 7) : d == 1 ? (k * N + ((j + 1) & 7)) * N + i
+                                                             : (((k + 1) & 7) * N + j) * N + i;
+  };
+  auto load = [&](int q, double (&U)[2][5]) {
+    if (q >= A.nblocks) return;
+    const double *__restrict__ st = A.state + A.blocks[__builtin_amdgcn_readfirstlane(A.ids[q])].off;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) U[h][v] = st[v * NC + tid + NT * h];
+  };
+
+  const int first = A.xcd_remap ? xcd_logical(blockIdx.x, gridDim.x) : blockIdx.x;
+  double Un[2][5] = {}, Unext[2][5] = {};
+  load(first, Unext);
+  for (int q = first; q < A.nblocks; q += gridDim.x) {
+    const int b = __builtin_amdgcn_readfirstlane(A.ids[q]);
+    const DevBlock &B = A.blocks[b];
+    double *__restrict__ st = A.state + B.off;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Un[h][v] = Unext[h][v];
+    load(q + gridDim.x, Unext);  // in flight while this block is computed
+    if (A.rate_only) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double Wd[5];
+        if (!recov(Un[h], Wd)) {
+          bad = 1;
+          badblk = min(badblk, b);
+        } else {
+          lam = fmax(lam, rate(Wd, B));
+        }
+      }
+      continue;
+    }
+    const double dtd[3] = {dt / B.dx[0], dt / B.dx[1], dt / B.dx[2]};
+    double Us[2][5];
+#pragma unroll
+    for (int stage = 1; stage <= 2; ++stage) {
+      // the stage source's primitives into LDS (stage 1 reports nothing: a bad
+      // Un was reported by the rate reduction that gave dt).  The previous
+      // stage's (or block's) last LDS reads were of F, behind a barrier
+      // after its last reads of W.
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double Wd[5];
+        if (!recov(stage == 1 ? Un[h] : Us[h], Wd) && stage == 2) {
+          bad = 1;
+          badblk = min(badblk, b);
+        }
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) W[v * NC + tid + NT * h] = (T)Wd[v];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        face(tid, d);
+        face(tid + NT, d);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = tid + NT * h;
+        const int cx = up(c, 0), cy = up(c, 1), cz = up(c, 2);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          const double fx = (double)F[0][v * NC + c] - (double)F[0][v * NC + cx];
+          const double fy = (double)F[1][v * NC + c] - (double)F[1][v * NC + cy];
+          const double fz = (double)F[2][v * NC + c] - (double)F[2][v * NC + cz];
+          double dU;
+          if constexpr (MIXED) {
+            dU = __builtin_fma(dtd[2], fz, __builtin_fma(dtd[1], fy, dtd[0] * fx));
+          } else {
+            dU = dtd[0] * fx;
+            dU += dtd[1] * fy;
+            dU += dtd[2] * fz;
+          }
+          if (stage == 1)
+            Us[h][v] = Un[h][v] + dU;
+          else
+            Us[h][v] = MIXED ? __builtin_fma(0.5, Un[h][v], 0.5 * (Us[h][v] + dU))
+                             : 0.5 * Un[h][v] + 0.5 * (Us[h][v] + dU);
+        }
+      }
+      // W is rewritten next only after every thread has passed the barrier
+      // above, i.e. after every face read of W; F is rewritten only after the
+      // next barrier, i.e. after every read of F
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) __builtin_nontemporal_store(Us[h][v], &st[v * NC + tid + NT * h]);
+      double Wd[5];
+      if (!recov(Us[h], Wd)) {
+        bad = 1;
+        badblk = min(badblk, b);
+      } else {
+        lam = fmax(lam, rate(Wd, B));
+      }
+    }
+  }
+  flush_acc(A.acc, lam, bad, badblk, true);
+}
+
 // CFL rate of the interior cells of the work list (FP64): in oracle order,
 // or (MIXED) with the mixed path's recovery and rate, as its stage 2 reduces
 // it.
@@ -1455,6 +1649,8 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
       const int64_t plane = (int64_t)B.n[0] * B.n[1];
       const double *p = A.src + B.off + (int64_t)y * B.n[0] + x;
       const int za = DIM == 3 ? it->z0 : 0, zb = DIM == 3 ? it->z1 : 1;
+      // unrolled so that the loads of several planes are in flight at once
+#pragma unroll 4
       for (int z = za; z < zb; ++z) {
         double W[5];
         if constexpr (MIXED) {
@@ -1483,17 +1679,17 @@ __global__ __launch_bounds__(WG) void k_lambda(StageArgs A) {
 // ------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------
-template <int DIM, bool MIXED, int STAGE, int SPEEDS, int RECON, int EOS = EOS_IDEAL>
+template <int DIM, bool MIXED, int STAGE, int SPEEDS, int RECON, int EOS = EOS_IDEAL, int OCC = 0>
 static hipError_t launch_ks(int kmask, int grid, hipStream_t s, const StageArgs &a) {
   switch (kmask) {
     case 1:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 1, SPEEDS, RECON, EOS, OCC>), dim3(grid), dim3(WG), 0, s, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 2, SPEEDS, RECON, EOS, OCC>), dim3(grid), dim3(WG), 0, s, a);
       break;
     default:
-      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS, RECON, EOS>), dim3(grid), dim3(WG), 0, s, a);
+      hipLaunchKernelGGL((k_stage<DIM, MIXED, STAGE, 3, SPEEDS, RECON, EOS, OCC>), dim3(grid), dim3(WG), 0, s, a);
       break;
   }
   return hipGetLastError();
@@ -1508,6 +1704,21 @@ static hipError_t launch_kr(int kmask, int speeds, int grid, hipStream_t s, cons
       return launch_ks<DIM, MIXED, STAGE, SPEEDS_PVRS, RECON>(kmask, grid, s, a);
     default:
       return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS, RECON>(kmask, grid, s, a);
+  }
+}
+
+// The default method (Davis bounds, primitive PLM, gamma law) with an
+// occupancy request of occ (2, 3 or 4) waves per SIMD instead of the
+// default register budget.
+template <int DIM, bool MIXED, int STAGE>
+static hipError_t launch_occ(int kmask, int occ, int grid, hipStream_t s, const StageArgs &a) {
+  switch (occ) {
+    case 2:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS, RECON_PRIMITIVE, EOS_IDEAL, 2>(kmask, grid, s, a);
+    case 3:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS, RECON_PRIMITIVE, EOS_IDEAL, 3>(kmask, grid, s, a);
+    default:
+      return launch_ks<DIM, MIXED, STAGE, SPEEDS_DAVIS, RECON_PRIMITIVE, EOS_IDEAL, 4>(kmask, grid, s, a);
   }
 }
 

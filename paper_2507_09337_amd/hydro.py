@@ -81,12 +81,14 @@ def lib():
             "hydro_batch_destroy": [vp],
             "hydro_batch_set_tiling": [vp, i32, i32, i32],
             "hydro_batch_set_launch": [vp, i32, i32],
+            "hydro_batch_set_occupancy": [vp, i32],
             "hydro_batch_autotune": [vp, dbl, i32],
             "hydro_batch_get_config": [vp, C.POINTER(C.c_int32), i32, C.POINTER(C.c_int32)],
             "hydro_batch_time_kernels": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
             "hydro_stream_create": [C.POINTER(BlockDesc), i32, i32, vp, i64, C.POINTER(C.c_int32), i32, i32, i32, pp],
             "hydro_stream_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
             "hydro_stream_destroy": [vp],
+            "hydro_stream_set_cpu_share": [vp, i32, i32],
             "hydro_step_static": [C.POINTER(BlockDesc), i32, i32, vp, i64, i32, dbl, dbl, vp],
         }
         for name, args in sig.items():
@@ -253,6 +255,10 @@ class Batch:
     def set_launch(self, grid: int, xcd_remap: int = 1):
         _check(lib().hydro_batch_set_launch(self.h, int(grid), int(xcd_remap)), "hydro_batch_set_launch")
 
+    def set_occupancy(self, waves: int):
+        """Register budget of `waves` (2..4) waves per SIMD for the stage kernels (0 = their own)."""
+        _check(lib().hydro_batch_set_occupancy(self.h, int(waves)), "hydro_batch_set_occupancy")
+
     def autotune(self, gamma: float, reps: int = 3, cache: str | None = None) -> dict:
         """Tune the batched launches in the library (tiling per block class,
         then grid and XCD renumbering; every candidate parity-checked) and
@@ -297,14 +303,15 @@ class Batch:
         for c in cfg["classes"]:
             self.set_tiling(c["edge"], c["tile"], c["zchunk"])
         self.set_launch(cfg["grid"], cfg["xcd_remap"])
+        self.set_occupancy(cfg.get("occupancy", 0))
 
     def config(self) -> dict:
-        buf = (C.c_int32 * (2 + 4 * 16))()
+        buf = (C.c_int32 * (3 + 4 * 16))()
         n = C.c_int32(0)
         _check(lib().hydro_batch_get_config(self.h, buf, 16, C.byref(n)), "hydro_batch_get_config")
-        classes = [{"edge": buf[2 + 4 * k], "tile": buf[3 + 4 * k], "zchunk": buf[4 + 4 * k], "cells": buf[5 + 4 * k]}
+        classes = [{"edge": buf[3 + 4 * k], "tile": buf[4 + 4 * k], "zchunk": buf[5 + 4 * k], "cells": buf[6 + 4 * k]}
                    for k in range(min(n.value, 16))]
-        return {"grid": buf[0], "xcd_remap": buf[1], "classes": classes}
+        return {"grid": buf[0], "xcd_remap": buf[1], "occupancy": buf[2], "classes": classes}
 
     def close(self):
         if self.h:
@@ -355,6 +362,12 @@ class HostStream:
         t = C.c_double(0.0)
         _check(lib().hydro_stream_run(self.h, int(nsteps), float(cfl), float(gamma), C.byref(t)), "hydro_stream_run")
         return t.value
+
+    def set_cpu_share(self, cpu_packets: int, nthreads: int = 0):
+        """Advance the last `cpu_packets` packets on the host cores (FP64 host
+        kernel, `nthreads` threads, 0 = all) while the GPU streams the rest."""
+        _check(lib().hydro_stream_set_cpu_share(self.h, int(cpu_packets), int(nthreads)),
+               "hydro_stream_set_cpu_share")
 
     def close(self):
         if self.h:

@@ -52,7 +52,7 @@ def _oracle(P):
     return R, dts, t
 
 
-def _gpu_run(P, prec, tune=False):
+def _gpu_run(P, prec, tune=False, fused=False):
     import torch
 
     arena = torch.from_numpy(P.U0).cuda()
@@ -61,6 +61,8 @@ def _gpu_run(P, prec, tune=False):
     b = H.Batch(pks)
     if tune:
         b.autotune(P.gamma, reps=2)
+    if fused:
+        b.set_tiling(8, 5)
     t = b.run(P.nsteps, P.cfl, P.gamma)
     torch.cuda.synchronize()
     U = arena.cpu().numpy()
@@ -69,10 +71,10 @@ def _gpu_run(P, prec, tune=False):
     return U, t
 
 
-def _check(P, R, t_ref, tune=False):
-    U, t = _gpu_run(P, H.FP64, tune)
+def _check(P, R, t_ref, tune=False, fused=False):
+    U, t = _gpu_run(P, H.FP64, tune, fused)
     e64 = rel_err(P.mesh, U, R)
-    U, tm = _gpu_run(P, H.FP32_FP64, tune)
+    U, tm = _gpu_run(P, H.FP32_FP64, tune, fused)
     l1 = l1_rho(P.mesh, U, R)
     et = abs(tm - t_ref) / t_ref
     print(f"{P.name}: fp64 max rel err {e64:.3e}, t err {abs(t - t_ref) / t_ref:.3e}; "
@@ -90,11 +92,23 @@ def test_smooth_full_size_100_steps():
     _check(P, R, t_ref)
 
 
-def test_uneven_full_size_20_steps_autotuned():
+@pytest.fixture(scope="module")
+def uneven_ref():
     P = I.uneven()
     assert P.mesh.nblocks == 6000 and P.nsteps == 20
     R, _, t_ref = _oracle(P)
+    return P, R, t_ref
+
+
+def test_uneven_full_size_20_steps_autotuned(uneven_ref):
+    P, R, t_ref = uneven_ref
     _check(P, R, t_ref, tune=True)
+
+
+def test_uneven_full_size_20_steps_fused(uneven_ref):
+    """The same with the 8^3 class on the fused step (tiling code 5)."""
+    P, R, t_ref = uneven_ref
+    _check(P, R, t_ref, fused=True)
 
 
 def test_packet_dt_mixed_and_fp64_against_oracle():
