@@ -462,6 +462,108 @@ def fused_class_study(P, steps, warmup):
     return out
 
 
+def secondary_paths(steps, warmup):
+    """The uneven workload (6000 self-periodic blocks of 8^3/16^3/32^3, 147
+    packets): the batched mixed and FP64 paths with the default tiling, the
+    fused step of its 8^3 class, and its state held in pinned host memory
+    (four GPU staging slots; GPU only, and with the last 8 packets on the host
+    cores).  Reported beside the headline, never as `value`."""
+    import torch
+
+    from paper_2507_09337_amd import hydro as H
+    from paper_2507_09337_amd import inputs as I
+
+    t0 = time.perf_counter()
+    P = I.uneven()
+    cells = P.mesh.total_cells
+    log(f"secondary workload {P.name}: {P.mesh.nblocks} blocks, {cells} cells, built in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": f"uneven: {P.mesh.nblocks} self-periodic blocks of 8^3/16^3/32^3, {cells} cells, "
+                       f"{len(P.packets)} packets, gamma {P.gamma}, CFL {P.cfl}", "steps": steps}
+    U0 = torch.from_numpy(P.U0).cuda()
+    arena = U0.clone()
+    mesh = H.Mesh(P.mesh, arena)
+    for prec, name in ((H.FP32_FP64, "batched_mixed"), (H.FP64, "batched_fp64")):
+        arena.copy_(U0)
+        b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+        b.run(warmup, P.cfl, P.gamma)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, ms = b.run_timed(steps, P.cfl, P.gamma)
+        el = time.perf_counter() - ts
+        b.close()
+        out[name] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "device_ms_per_step": float(np.mean(ms))}
+        log("secondary", name, json.dumps(out[name]))
+    mesh.close()
+    del arena, U0
+    torch.cuda.empty_cache()
+    out["fused_8cube_class"] = fused_class_study(P, steps, warmup)
+    nthreads = len(os.sched_getaffinity(0))
+    for k in (0, 8):
+        host = torch.from_numpy(P.U0.copy()).pin_memory()
+        hs = H.HostStream(P.mesh, host, P.packets, H.FP32_FP64, 4)
+        hs.set_cpu_share(k, nthreads)
+        hs.run(1, P.cfl, P.gamma)
+        ts = time.perf_counter()
+        hs.run(steps, P.cfl, P.gamma)
+        el = time.perf_counter() - ts
+        hs.close()
+        key = "host_resident_mixed" + (f"_cpu{k}" if k else "")
+        out[key] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                    "pcie_gbs": 80.0 * cells * steps / el / 1e9, "cpu_packets": k, "cpu_threads": nthreads,
+                    "note": "PCIe-inclusive (state in pinned host memory)"}
+        log("secondary", key, json.dumps(out[key]))
+    return out
+
+
+def summarize_valu(args):
+    """Markdown summary of a rocprofv3 run with the VALU counters
+    (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_WAVES, GRBM_GUI_ACTIVE) and,
+    optionally, one with the L2 counters (TCC_HIT_sum, TCC_MISS_sum), per
+    stage kernel of the large workload, written to stdout."""
+    cells = 32768 * 4096
+    vals = {}
+    for d in (args.valu, args.tcc):
+        if not d:
+            continue
+        for r in _csv_rows(d, "counter_collection.csv"):
+            name = r.get("Kernel_Name", "")
+            if "k_stage<3" not in name and "k_fused" not in name:
+                continue
+            disp = r.get("Dispatch_Id", "")
+            vals.setdefault(name, {}).setdefault(r["Counter_Name"], {}).setdefault(disp, 0.0)
+            vals[name][r["Counter_Name"]][disp] += float(r["Counter_Value"])
+    lines = ["# VALU work and L2 hits of the stage kernels on the large workload (32768 blocks of 16^3 = "
+             "134217728 cells)", "",
+             "Workload: Sedov deposit + 1 % density noise, periodic, gamma 1.4, CFL 0.4; batched launches; every "
+             "method variant the benchmark times.", "", "## Commands", "", "```", "cd /tmp && export TMPDIR=/tmp"]
+    lines += list(args.cmd) + ["```", "",
+                               "Per dispatch, averaged over the dispatches of each kernel: VALU instructions per cell = "
+                               "SQ_INSTS_VALU (wave instructions, summed over all shader engines) x 64 lanes / cells; "
+                               "VALU busy = 100 x SQ_ACTIVE_INST_VALU / 256 CUs / (GRBM_GUI_ACTIVE / 8 XCDs); L2 hit "
+                               "rate = TCC_HIT / (TCC_HIT + TCC_MISS).", "",
+                               "| Kernel | Dispatches | VALU instr / cell | VALU busy % | L2 hit % |",
+                               "|---|---|---|---|---|"]
+
+    def mean(name, counter):
+        d = vals[name].get(counter)
+        return (float(np.mean(list(d.values()))), len(d)) if d else (None, 0)
+
+    for name in sorted(vals):
+        iv, n = mean(name, "SQ_INSTS_VALU")
+        av, _ = mean(name, "SQ_ACTIVE_INST_VALU")
+        gg, _ = mean(name, "GRBM_GUI_ACTIVE")
+        hit, _ = mean(name, "TCC_HIT_sum")
+        mis, _ = mean(name, "TCC_MISS_sum")
+        per = f"{iv * 64 / cells:.0f}" if iv is not None else "-"
+        busy = f"{100 * av / 256 / (gg / 8):.1f}" if av is not None and gg else "-"
+        hr = f"{100 * hit / (hit + mis):.1f}" if hit is not None and mis is not None and hit + mis > 0 else "-"
+        lines.append(f"| `{name}` | {n} | {per} | {busy} | {hr} |")
+    lines += ["", f"Kernel sources (stage_kernels.h, kernels_inst.hip, hydro_internal.h) sha256 at measurement: "
+                  f"`{kernel_source_sha()}`"]
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,6 +571,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--repeats", type=int, default=5, help="repetitions of the timed region (median reported)")
     ap.add_argument("--no-probe", action="store_true", help="skip the HBM streaming-kernel sweep")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the uneven-workload paths (batched, fused 8^3 class, host-resident, CPU/GPU split)")
     ap.add_argument("--workload", default="large")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-packet FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -484,9 +588,15 @@ def main():
     ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output directory")
     ap.add_argument("--cmd", action="append", default=[], help="command line to list in the summary")
     ap.add_argument("--bench-line", help="file holding the JSON line of the kernel-trace run")
+    ap.add_argument("--summarize-valu", action="store_true",
+                    help="instead: write the markdown summary of the VALU (--valu dir) and L2 (--tcc dir) counters")
+    ap.add_argument("--valu", help="rocprofv3 --pmc SQ_INSTS_VALU ... output directory")
+    ap.add_argument("--tcc", help="rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum output directory")
     args = ap.parse_args()
     if args.summarize_profiles:
         return summarize_profiles(args)
+    if args.summarize_valu:
+        return summarize_valu(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built.",
               file=sys.stderr)
@@ -704,6 +814,11 @@ def main():
     }
     if "plain_fp64" in results:
         line["speedup_vs_plain_fp64"] = head["cell_updates_per_s"] / results["plain_fp64"]["cell_updates_per_s"]
+    if P.name == "sedov_noise" and not args.no_secondary:
+        del arena, U0_dev
+        mesh.close()
+        torch.cuda.empty_cache()
+        line["secondary"] = secondary_paths(min(args.steps, 10), min(args.warmup, 2))
     print(json.dumps(line), flush=True)
 
 
