@@ -275,7 +275,8 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  *               first-stage state never goes to memory (80 instead of 200
  *               bytes per cell-update; the communication-avoiding step of
  *               the paper's Sec. 6 for blocks whose halo is their own
- *               interior);
+ *               interior); in hydro_batch_run the fused launch is a branch
+ *               of the step graph beside the two stage launches;
  *   zchunk: z planes per work item (0 = the whole block; 3D only).
  * Without a setting a class uses 16x16 tiles (8x8 if its extents need them)
  * on whole blocks, in z-runs of two when the class has at least 12 x (number
@@ -286,7 +287,10 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * persistent grid of that many workgroups looping over the work list), and
  * xcd_remap = 1 renumbers workgroups so that each of the GPU's 8 XCDs (each
  * with its own L2) runs a contiguous span of the work list, keeping
- * neighbouring blocks' guard reads in one L2 (0 = hardware order).
+ * neighbouring blocks' guard reads in one L2 (0 = hardware order; the
+ * default is 1 when a block of the batch links to a neighbour, else 0).
+ * Work items are launched heaviest first (planes times tile cells; items of
+ * equal work in block order).
  * hydro_batch_set_tiling(b, edge, tile, zchunk) and hydro_batch_set_launch
  * rebuild or relaunch accordingly (EINVAL for a tile the class cannot use, or
  * a value out of range, or a fused step the class cannot take).

@@ -129,6 +129,8 @@ struct hydro_batch {
   int nfused = 0;
   DevTime *d_time = nullptr;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side_stream = nullptr;  // the fused launch's branch of a captured step
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double g_cfl = 0.0, g_gamma = 0.0;
@@ -231,6 +233,33 @@ int default_run(const hydro_mesh *m, int64_t tiles) {
   return (m->ndim == 3 && m->num_cu > 0 && tiles / 2 >= 2 * 3 * (int64_t)m->num_cu) ? 2 : 1;
 }
 
+// Work of an item in cell-planes: the planes it marches times the cells of
+// its tiles.
+int64_t item_cost(const hydro_mesh *m, const WorkItem &it) {
+  int64_t c = 0;
+  for (int s = 0; s < 4; ++s) {
+    if (it.block[s] < 0) continue;
+    const int planes = it.kind == hyd::KIND_T16 && s > 0 ? m->desc[it.block[s]].n[2] : it.z1 - it.z0;
+    c += (int64_t)planes * (it.kind == hyd::KIND_T16 ? 256 : 64);
+  }
+  return c;
+}
+
+// Heaviest items first (a stable sort: items of equal work keep the block
+// order that puts neighbouring blocks next to each other).  On uneven blocks
+// the big items then start in the first rounds and the small ones fill the
+// last, instead of a few big items running alone at the end of a launch.
+void order_items(const hydro_mesh *m, std::vector<WorkItem> &items) {
+  std::vector<int64_t> cost(items.size());
+  for (size_t i = 0; i < items.size(); ++i) cost[i] = item_cost(m, items[i]);
+  std::vector<size_t> idx(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<WorkItem> out(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) out[i] = items[idx[i]];
+  items.swap(out);
+}
+
 // Items in block order; 8x8 tiles are packed four to an item (tiles of equal
 // z range only).  Blocks of a class tiled in z-runs (3D, whole blocks) are
 // chained along their +z links within `ids` and cut into runs of k blocks;
@@ -329,7 +358,10 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
   }
   for (auto &kv : pending)
     if (!kv.second.empty()) emit8(kv.second, kv.first.first, kv.first.second);
-  if (pos.empty()) return;
+  if (pos.empty()) {
+    order_items(m, items);
+    return;
+  }
 
   // z columns of the run-tiled blocks: b -> b' along +z when b' is b's +z
   // neighbour, b is b''s -z neighbour, and both are run-tiled with equal
@@ -390,6 +422,7 @@ void build_items(const hydro_mesh *m, const std::vector<int32_t> &ids, const std
           kmask |= 1;
         }
     }
+  order_items(m, items);
 }
 
 hydro_status upload_items(const std::vector<WorkItem> &items, int kmask, WorkList &wl, hipStream_t s) {
@@ -709,11 +742,25 @@ hydro_status hydro_batch_create(hydro_packet *const *packets, int32_t npackets, 
   bt->packets.assign(packets, packets + npackets);
   bt->ids = std::move(ids);
   bt->prec = prec;
+  // XCD renumbering pays where neighbouring blocks read each other's cells;
+  // blocks that link to none gain nothing from sharing an L2, and contiguous
+  // spans of uneven items would load the XCDs unevenly
+  bool linked = false;
+  for (int b : bt->ids)
+    for (int f = 0; f < 2 * m->ndim; ++f) linked = linked || m->desc[b].face_kind[f] == HYDRO_NBR;
+  bt->remap = linked ? 1 : 0;
   hydro_status st = rebuild_batch_items(bt);
   if (!st) st = alloc_time(&bt->d_time, m->stream);
-  if (!st && hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking) != hipSuccess)
-    st = fail(HYDRO_EDEVICE, "batch: stream creation failed");
+  if (!st && (hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+              hipStreamCreateWithFlags(&bt->side_stream, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&bt->fork_ev, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&bt->join_ev, hipEventDisableTiming) != hipSuccess))
+    st = fail(HYDRO_EDEVICE, "batch: stream or event creation failed");
   if (st) {
+    if (bt->fork_ev) (void)hipEventDestroy(bt->fork_ev);
+    if (bt->join_ev) (void)hipEventDestroy(bt->join_ev);
+    if (bt->side_stream) (void)hipStreamDestroy(bt->side_stream);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     if (bt->wl.d_items) (void)hipFree(bt->wl.d_items);
     if (bt->d_fused) (void)hipFree(bt->d_fused);
     if (bt->d_time) (void)hipFree(bt->d_time);
@@ -732,6 +779,9 @@ hydro_status hydro_batch_destroy(hydro_batch *b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->join_ev) (void)hipEventDestroy(b->join_ev);
   (void)hipFree(b->wl.d_items);
   if (b->d_fused) (void)hipFree(b->d_fused);
   (void)hipFree(b->d_time);
@@ -769,15 +819,28 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   b->graph = nullptr;
   const int prec = b->prec;
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-  hydro_status st = launch_stage_wl(m, prec, 1, b->wl, b->grid, b->cap_stream,
-                                    stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
+  hydro_status st = HYDRO_OK;
+  // The fused blocks share no cells with the others, so their launch is a
+  // branch of the graph beside the two stage launches (both branches fold
+  // their CFL rate into the accumulator with atomics); the dt update waits
+  // for both.
+  if (b->nfused > 0) {
+    if (hipEventRecord(b->fork_ev, b->cap_stream) != hipSuccess ||
+        hipStreamWaitEvent(b->side_stream, b->fork_ev, 0) != hipSuccess ||
+        hyd::launch_fused(is_mixed(prec), b->nfused, b->side_stream,
+                          fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
+                                     b->remap)) != hipSuccess ||
+        hipEventRecord(b->join_ev, b->side_stream) != hipSuccess)
+      st = fail(HYDRO_EDEVICE, "fused step branch capture failed");
+  }
+  if (!st)
+    st = launch_stage_wl(m, prec, 1, b->wl, b->grid, b->cap_stream,
+                         stage_args(m, b->wl, 1, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
   if (!st)
     st = launch_stage_wl(m, prec, 2, b->wl, b->grid, b->cap_stream,
                          stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
-  if (!st && hyd::launch_fused(is_mixed(prec), b->nfused, b->cap_stream,
-                               fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
-                                          b->remap)) != hipSuccess)
-    st = fail(HYDRO_EDEVICE, "fused step launch failed");
+  if (!st && b->nfused > 0 && hipStreamWaitEvent(b->cap_stream, b->join_ev, 0) != hipSuccess)
+    st = fail(HYDRO_EDEVICE, "fused step branch join failed");
   if (!st && hyd::launch_finalize(b->d_time, cfl, 0, b->cap_stream) != hipSuccess)
     st = fail(HYDRO_EDEVICE, "finalize launch failed");
   hipGraph_t g = nullptr;
@@ -1546,11 +1609,18 @@ static hydro_status time_full(hydro_batch *b, double gamma, int reps, double &ms
   a2.un = m->u1;
   a2.dst = m->u1;
   const hyd::FusedArgs af = fused_args(m, b->d_fused, b->nfused, m->u1, dt, nullptr, b->d_time, gamma, 0, b->remap);
-  auto step = [&]() -> hydro_status {
-    hydro_status s2 = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, a1, b->occ);
-    if (!s2) s2 = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream, a2, b->occ);
-    if (!s2 && hyd::launch_fused(is_mixed(prec), b->nfused, m->stream, af) != hipSuccess)
+  auto step = [&]() -> hydro_status {  // as in a captured step: the fused launch beside the stage launches
+    hydro_status s2 = HYDRO_OK;
+    if (b->nfused > 0 &&
+        (hipEventRecord(b->fork_ev, m->stream) != hipSuccess ||
+         hipStreamWaitEvent(b->side_stream, b->fork_ev, 0) != hipSuccess ||
+         hyd::launch_fused(is_mixed(prec), b->nfused, b->side_stream, af) != hipSuccess ||
+         hipEventRecord(b->join_ev, b->side_stream) != hipSuccess))
       s2 = fail(HYDRO_EDEVICE, "tuning: fused launch failed");
+    if (!s2) s2 = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, a1, b->occ);
+    if (!s2) s2 = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream, a2, b->occ);
+    if (!s2 && b->nfused > 0 && hipStreamWaitEvent(m->stream, b->join_ev, 0) != hipSuccess)
+      s2 = fail(HYDRO_EDEVICE, "tuning: fused join failed");
     return s2;
   };
   hipEvent_t e0, e1;
