@@ -290,6 +290,27 @@ def measured_traffic(kernel_names):
     return total
 
 
+def measured_valu(kernel_names):
+    """VALU instructions per cell of the given kernels from the committed
+    counter summary, or None when it is missing or was taken on a different
+    version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", "stage_kernels_valu_large.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if kernel_source_sha() not in text:
+        return None
+    per = {}
+    for line in text.splitlines():
+        if line.startswith("| `"):
+            cols = [c.strip() for c in line.strip("|").split("|")]
+            per[cols[0].strip("`")] = cols[2]
+    try:
+        return sum(float(per[k]) for k in kernel_names)
+    except (KeyError, ValueError):
+        return None
+
+
 def _csv_rows(directory, suffix):
     import csv
     import glob
@@ -797,6 +818,20 @@ def main():
         roofline.update({"copy_probe_gbs": probe["gbs"], "frac_of_copy_probe": achieved / probe["gbs"],
                          "hbm_ceiling": {k: probe[k] for k in ("best_copy", "best_read", "best_write", "configs")}})
     ach64 = BYTES_PER_CELL_UPDATE * cells / (results["batched_fp64"]["device_ms_per_step"] * 1e-3) / 1e9
+    # the FP64 path is bound by its vector ALU issue: one wave64 instruction per CU per cycle
+    valu64 = measured_valu(["void hyd::k_stage<3, false, 1, 1, 0, 0, 0, 0>(hyd::StageArgs)",
+                            "void hyd::k_stage<3, false, 2, 1, 0, 0, 0, 0>(hyd::StageArgs)"]) \
+        if P.name == "sedov_noise" else None
+    roof64 = None
+    if valu64:
+        issue = 256 * 2.4e9 * 64  # lane-instructions per second (256 CUs, 2.4 GHz, wave64)
+        dev64 = results["batched_fp64"]["device_ms_per_step"] * 1e-3
+        roof64 = {"bound": "alu", "achieved": valu64 * cells / dev64 / 1e12, "peak": issue / 1e12,
+                  "unit": "T lane-instructions/s", "frac": valu64 * cells / dev64 / issue,
+                  "valu_instructions_per_cell_update": valu64,
+                  "note": "VALU instructions per cell of the FP64 stage kernels from "
+                          "profiles/stage_kernels_valu_large.md (PMC SQ_INSTS_VALU) over the batched FP64 step's "
+                          "device time, against one wave64 instruction per CU per cycle"}
 
     line = {
         "metric": METRIC,
@@ -819,6 +854,7 @@ def main():
         "cpu_baseline": cpu,
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "config"} for k, v in results.items()},
         "batched_fp64_roofline_frac": ach64 / HBM_PEAK_GBS,
+        "batched_fp64_valu_roofline": roof64,
         "tuning": results["batched_mixed"]["config"],
         "errors_vs_oracle": errs,
         "variants_kernel_time": variants,
