@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -1851,6 +1852,8 @@ static_assert(sizeof(SetupChunk) <= 4096, "setup kernel arguments must stay with
 static_assert(sizeof(DevBlock) == 176 && sizeof(WorkItem) == 40, "the static step's size limit in hydro.h counts these sizes");
 
 std::atomic<void *> g_scratch_addr[kMaxDevices];
+std::pair<int64_t, int64_t> g_static_ranges[kStaticMaxBlocks];
+std::mutex g_static_ranges_mu;
 
 }  // namespace
 
@@ -1902,8 +1905,12 @@ hydro_status hydro_step_static(const hydro_block_desc *blocks, int32_t nblocks, 
                                int64_t arena_len, int32_t precision, double dt, double gamma, void *stream) {
   if (nblocks > kStaticMaxBlocks)
     return failf(HYDRO_EINVAL, "static step: %d blocks, at most %d", (int)nblocks, kStaticMaxBlocks);
-  std::pair<int64_t, int64_t> ranges[kStaticMaxBlocks];
-  hydro_status st = validate_blocks(blocks, nblocks, ndim, arena, arena_len, ranges);
+  hydro_status st;
+  {  // the overlap check sorts block ranges in a fixed host array (no
+     // allocation, and nothing large on the caller's stack)
+    std::lock_guard<std::mutex> lock(g_static_ranges_mu);
+    st = validate_blocks(blocks, nblocks, ndim, arena, arena_len, g_static_ranges);
+  }
   if (st) return st;
   if (!prec_valid(precision)) return failf(HYDRO_EINVAL, "static step: bad precision");
   if (!finite_pos(dt)) return failf(HYDRO_EINVAL, "dt must be finite and > 0");
