@@ -481,7 +481,7 @@ StageArgs stage_args(const hydro_mesh *m, const WorkList &wl, int stage, double 
 
 int grid_of(const WorkList &wl, int grid) { return grid > 0 ? std::min(grid, wl.nitems) : wl.nitems; }
 
-// Arguments of the batch's fused-step launch (one workgroup per fused block).
+// Arguments of the batch's fused-step launch.
 hyd::FusedArgs fused_args(const hydro_mesh *m, const int32_t *ids, int n, double *state, double dt,
                           const DevTime *dt_dev, DevTime *acc, double gamma, int rate_only, int remap) {
   hyd::FusedArgs a;
@@ -515,6 +515,16 @@ bool is_mixed(int32_t p) { return (p & 0xff) == HYDRO_FP32_FP64; }
 int speeds_of(int32_t p) { return (p & HYDRO_SPEEDS_EINFELDT) ? 1 : (p & HYDRO_SPEEDS_PVRS) ? 2 : 0; }
 int recon_of(int32_t p) { return (p & HYDRO_RECON_CONSERVED) ? 1 : (p & HYDRO_RECON_CHARACTERISTIC) ? 2 : 0; }
 int eos_of(int32_t p) { return (p & HYDRO_EOS_GAS_RADIATION) ? 1 : 0; }
+
+// Workgroups of the batch's fused-step launch: as many as can be resident
+// (three per CU for the mixed kernel, two for the FP64 one, whose LDS and
+// registers allow no more), each looping over its share of the blocks and
+// loading the next block while it computes the current one.
+int fused_grid(const hydro_batch *b) {
+  const int resident = (is_mixed(b->prec) ? 3 : 2) * std::max(b->m->num_cu, 1);
+  return std::min(b->nfused, resident);
+}
+
 
 hydro_status launch_stage_wl(const hydro_mesh *m, int prec, int stage, const WorkList &wl, int grid,
                              hipStream_t s, const StageArgs &a, int occ = 0) {
@@ -828,7 +838,7 @@ static hydro_status capture_step(hydro_batch *b, double cfl, double gamma) {
   if (b->nfused > 0) {
     if (hipEventRecord(b->fork_ev, b->cap_stream) != hipSuccess ||
         hipStreamWaitEvent(b->side_stream, b->fork_ev, 0) != hipSuccess ||
-        hyd::launch_fused(is_mixed(prec), b->nfused, b->side_stream,
+        hyd::launch_fused(is_mixed(prec), fused_grid(b), b->side_stream,
                           fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
                                      b->remap)) != hipSuccess ||
         hipEventRecord(b->join_ev, b->side_stream) != hipSuccess)
@@ -884,7 +894,7 @@ static hydro_status batch_run(hydro_batch *b, int32_t nsteps, double cfl, double
     e = hyd::launch_lambda(m->ndim, is_mixed(b->prec), b->wl.kmask, eos_of(b->prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess)
-    e = hyd::launch_fused(is_mixed(b->prec), b->nfused, m->stream,
+    e = hyd::launch_fused(is_mixed(b->prec), fused_grid(b), m->stream,
                           fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, nullptr, b->d_time, gamma, 1, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("batch run setup: ") + hipGetErrorString(e));
@@ -939,7 +949,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
     e = hyd::launch_lambda(m->ndim, is_mixed(prec), b->wl.kmask, eos_of(prec), grid_of(b->wl, b->grid), m->stream,
                            stage_args(m, b->wl, 1, 0.0, nullptr, b->d_time, gamma, 0, b->remap));
   if (e == hipSuccess)
-    e = hyd::launch_fused(is_mixed(prec), b->nfused, m->stream,
+    e = hyd::launch_fused(is_mixed(prec), fused_grid(b), m->stream,
                           fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, nullptr, b->d_time, gamma, 1, b->remap));
   if (e == hipSuccess) e = hyd::launch_finalize(b->d_time, cfl, 1, m->stream);
   if (e != hipSuccess) return fail(HYDRO_EDEVICE, std::string("timing setup: ") + hipGetErrorString(e));
@@ -954,7 +964,7 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
     if (!st)
       st = launch_stage_wl(m, prec, 2, b->wl, b->grid, m->stream,
                            stage_args(m, b->wl, 2, 0.0, b->d_time, b->d_time, gamma, 0, b->remap), b->occ);
-    if (!st && hyd::launch_fused(is_mixed(prec), b->nfused, m->stream,
+    if (!st && hyd::launch_fused(is_mixed(prec), fused_grid(b), m->stream,
                                  fused_args(m, b->d_fused, b->nfused, m->arena, 0.0, b->d_time, b->d_time, gamma, 0,
                                             b->remap)) != hipSuccess)
       st = fail(HYDRO_EDEVICE, "fused step launch failed");
@@ -1615,7 +1625,7 @@ static hydro_status time_full(hydro_batch *b, double gamma, int reps, double &ms
     if (b->nfused > 0 &&
         (hipEventRecord(b->fork_ev, m->stream) != hipSuccess ||
          hipStreamWaitEvent(b->side_stream, b->fork_ev, 0) != hipSuccess ||
-         hyd::launch_fused(is_mixed(prec), b->nfused, b->side_stream, af) != hipSuccess ||
+         hyd::launch_fused(is_mixed(prec), fused_grid(b), b->side_stream, af) != hipSuccess ||
          hipEventRecord(b->join_ev, b->side_stream) != hipSuccess))
       s2 = fail(HYDRO_EDEVICE, "tuning: fused launch failed");
     if (!s2) s2 = launch_stage_wl(m, prec, 1, b->wl, b->grid, m->stream, a1, b->occ);

@@ -136,3 +136,24 @@ def test_fused_refused_for_other_blocks():
             b.set_tiling(8, 5)
         assert e.value.code == H.EINVAL
         mesh.close()
+
+
+@pytest.mark.parametrize("prec", [H.FP64, H.FP32_FP64], ids=["fp64", "mixed"])
+def test_graph_replays_match_eager_steps(uneven, prec):
+    """The captured step graph (stage launches plus the fused branch) replayed
+    one step at a time, with eager work and synchronisations between the
+    replays, equals the same steps launched eagerly (hydro_batch_time_kernels),
+    bitwise after every step."""
+    P = uneven[0]
+    arena_g, arena_e = to_dev(P.U0), to_dev(P.U0)
+    mesh_g, mesh_e = H.Mesh(P.mesh, arena_g), H.Mesh(P.mesh, arena_e)
+    bg = _fused_batch(mesh_g, P, prec)
+    be = _fused_batch(mesh_e, P, prec)
+    for s in range(4):
+        bg.run(1, P.cfl, P.gamma)  # one graph replay (the graph is captured once, on the first call)
+        be.time_kernels(1, P.cfl, P.gamma)  # the same step, eager launches
+        scratch = to_dev(np.arange(1000, dtype=np.float64)) * 2.0  # eager work of the program between replays
+        assert float(scratch.sum()) == 999000.0
+        assert np.array_equal(to_host(arena_g), to_host(arena_e)), s
+    mesh_g.close()
+    mesh_e.close()
