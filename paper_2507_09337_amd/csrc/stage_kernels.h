@@ -1212,10 +1212,15 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
       fetch(src + off, vs, U);
     }
   };
+  // Stage 1 fetches the guard ring two planes ahead (its registers allow
+  // the second buffer; stage 2, held to three waves, fetches one ahead).
+  constexpr bool G2 = STAGE == 1;
+  double Gr2[5] = {0, 0, 0, 0, 0};
   fetch_z(C.z0 - 2, Ud);
   fetch_z(C.z0 - 1, Ub);
   fetch_z(C.z0, Uc);
   fetch_guard(C.z0, Gr);
+  if (G2 && C.z0 + 1 < C.z1) fetch_guard(C.z0 + 1, Gr2);
   if (active) {
     prims(Ud, Wa, true);
     prims(Ub, Wb, true);
@@ -1309,13 +1314,20 @@ __device__ __forceinline__ void run_tile_mixed(const StageArgs &A, const WorkIte
     if (s > 0) {
       tile_setup<TX, TX, DIM>(C, A, it, s, lt, dt, PX);
       uniform_ctx();
-      fetch_guard(C.z0, Gr);  // the new block's guard cells of its first plane
+      fetch_guard(C.z0, Gr);  // the new block's guard cells of its first plane(s)
+      if (G2 && C.z0 + 1 < C.z1) fetch_guard(C.z0 + 1, Gr2);
     }
     for (int j = C.z0; j < C.z1; ++j) {
       fetch_z(j + 2, Ud);
       fetch_un(j, Un);
       stage_plane(Wb, Gr);
-      if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
+      if constexpr (G2) {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) Gr[v] = Gr2[v];
+        if (j + 2 < C.z1) fetch_guard(j + 2, Gr2);
+      } else {
+        if (j + 1 < C.z1) fetch_guard(j + 1, Gr);
+      }
       __syncthreads();
       // x and y faces, then the z face (register work, no LDS), then the
       // leftover faces of job 2: one straight run of independent work
@@ -1379,7 +1391,7 @@ constexpr size_t stage_lds_bytes() {
 // of OCC waves: 2, 3 or 4), a candidate of the autotuner.
 template <int DIM, bool MIXED, int STAGE, int KMASK, int SPEEDS, int RECON, int EOS, int OCC = 0>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(
-    OCC > 0 ? OCC : (MIXED ? STAGE == 2 : (STAGE == 1 && KMASK == 1 && EOS == EOS_IDEAL)) ? 3 : 1)))
+    OCC > 0 ? OCC : (MIXED ? true : (STAGE == 1 && KMASK == 1 && EOS == EOS_IDEAL)) ? 3 : 1)))
 void k_stage(StageArgs A) {
   static_assert(EOS == EOS_IDEAL || !MIXED, "the gas + radiation EOS runs on the FP64 tile only");
   __shared__ __attribute__((aligned(16))) unsigned char lds[stage_lds_bytes<KMASK, MIXED>()];
