@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-updates/s and % HBM roofline, FP32-batched vs FP64-plain, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = 200.0
+HOST_UNIT_BYTES = 64 << 20  # transfer unit of the host-resident packet lines (0 = one packet per unit)
 
 
 def log(*a):
@@ -416,26 +417,28 @@ def host_packets_bench(args):
     cells = P.mesh.total_cells
     out = {}
     for prec, name in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
-        for nslots in (1, 3, 4):
+        for nslots, unit in ((1, 0), (3, 0), (4, 0), (3, HOST_UNIT_BYTES), (4, HOST_UNIT_BYTES)):
             host = torch.from_numpy(P.U0.copy()).pin_memory()
             hs = H.HostStream(P.mesh, host, P.packets, prec, nslots)
+            hs.set_unit_bytes(unit)
             hs.run(args.warmup, P.cfl, P.gamma)
             ts = time.perf_counter()
             hs.run(args.steps, P.cfl, P.gamma)
             el = time.perf_counter() - ts
             hs.close()
-            out[f"{name}_slots{nslots}"] = {"cell_updates_per_s": cells * args.steps / el,
-                                            "ms_per_step": 1e3 * el / args.steps,
-                                            "pcie_gbs": 80.0 * cells * args.steps / el / 1e9}
-            log(name, nslots, json.dumps(out[f"{name}_slots{nslots}"]))
+            key = f"{name}_slots{nslots}" + (f"_unit{unit >> 20}MiB" if unit else "")
+            out[key] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                        "pcie_gbs": 80.0 * cells * args.steps / el / 1e9, "unit_bytes": unit}
+            log(name, nslots, unit, json.dumps(out[key]))
     # CPU/GPU split (the paper's blocks-per-cycle split between host cores and GPU): the last k packets on
-    # the host cores, the rest streamed through four GPU slots
+    # the host cores, the rest streamed through four GPU slots in transfer units of HOST_UNIT_BYTES
     split = {}
     nthreads = len(os.sched_getaffinity(0))
     for prec, name in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
         for k in (0, 4, 8, 16, 24, 32, 48):
             host = torch.from_numpy(P.U0.copy()).pin_memory()
             hs = H.HostStream(P.mesh, host, P.packets, prec, 4)
+            hs.set_unit_bytes(HOST_UNIT_BYTES)
             hs.set_cpu_share(k, nthreads)
             hs.run(args.warmup, P.cfl, P.gamma)
             ts = time.perf_counter()
@@ -535,6 +538,7 @@ def secondary_paths(steps, warmup):
     for k in (0, 8):
         host = torch.from_numpy(P.U0.copy()).pin_memory()
         hs = H.HostStream(P.mesh, host, P.packets, H.FP32_FP64, 4)
+        hs.set_unit_bytes(HOST_UNIT_BYTES)
         hs.set_cpu_share(k, nthreads)
         hs.run(1, P.cfl, P.gamma)
         ts = time.perf_counter()
@@ -544,7 +548,9 @@ def secondary_paths(steps, warmup):
         key = "host_resident_mixed" + (f"_cpu{k}" if k else "")
         out[key] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
                     "pcie_gbs": 80.0 * cells * steps / el / 1e9, "cpu_packets": k, "cpu_threads": nthreads,
-                    "note": "PCIe-inclusive (state in pinned host memory)"}
+                    "unit_bytes": HOST_UNIT_BYTES,
+                    "note": "PCIe-inclusive (state in pinned host memory); four staging slots; consecutive GPU "
+                            "packets copied and advanced in transfer units of at least unit_bytes"}
         log("secondary", key, json.dumps(out[key]))
     return out
 

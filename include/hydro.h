@@ -347,16 +347,18 @@ hydro_status hydro_batch_time_kernels(hydro_batch *b, int32_t nsteps, double cfl
  * + 5 * its cell count) and the packet must be closed (every HYDRO_NBR face
  * of its blocks names a block of the same packet), so that it takes a full
  * SSP-RK2 step on its own.  nslots (1..16) device staging slots, each with
- * its own stream (default priority) and buffers sized for the largest packet,
- * take the packets in order, each packet going to the slot with the fewest
- * bytes so far: packet p is copied in, advanced (one launch per RK stage) and
- * copied back on its slot's stream, so one packet's copies overlap other
- * packets' copies and kernels.  dt = cfl / max rate over all packets, from the
+ * its own stream (default priority) and buffers sized for the largest
+ * transfer unit (one packet by default, see hydro_stream_set_unit_bytes),
+ * take the units in order, each going to the slot with the fewest bytes so
+ * far: a unit is copied in, advanced (one launch per RK stage) and copied
+ * back on its slot's stream, so one unit's copies overlap other units'
+ * copies and kernels.  dt = cfl / max rate over all packets, from the
  * state at the start of each step, stays on the device: the control stream
  * waits for every slot's last stage-2 launch of a step, updates dt, and each
  * slot waits for that update only after it has issued the copy-in of its
- * first packet of the next step.  All device memory is allocated by create.
- * Errors (create): EINVAL (descriptors as for hydro_mesh_create, packet
+ * first unit of the next step.  All device memory is allocated by create
+ * (and, when a larger transfer unit is asked for, by
+ * hydro_stream_set_unit_bytes).  Errors (create): EINVAL (descriptors as for hydro_mesh_create, packet
  * ranges, non-contiguous packet, open packet, nslots, precision), ENOMEM,
  * EDEVICE. */
 typedef struct hydro_stream hydro_stream;
@@ -386,6 +388,17 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
  * method variant takes no host share (EINVAL); on a mixed-precision stream
  * the host packets still compute in FP64.  Errors: EINVAL, ENOMEM. */
 hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, int32_t nthreads);
+
+/* Transfer granularity of a stream (the paper's packet size knob, Sec. 6.1:
+ * packets amortise the cost of each transfer and each launch).  Consecutive
+ * GPU packets that are adjacent in the host arena are copied in, advanced
+ * (one launch per RK stage over all of them) and copied back together, in
+ * units of at least min_bytes each (the last unit may be smaller; a single
+ * packet larger than min_bytes is a unit of its own); min_bytes = 0, the
+ * default, keeps one packet per unit.  The staging slots grow to the
+ * largest unit.  Results are the same bit for bit at any setting.  Errors:
+ * EINVAL, ENOMEM, EDEVICE. */
+hydro_status hydro_stream_set_unit_bytes(hydro_stream *s, int64_t min_bytes);
 
 hydro_status hydro_stream_destroy(hydro_stream *s);
 

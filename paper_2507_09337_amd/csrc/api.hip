@@ -1009,8 +1009,17 @@ struct hydro_stream {
   std::vector<int32_t> pstart;     // npackets + 1
   std::vector<int64_t> phost;      // host element offset of each packet
   std::vector<int64_t> plen;       // elements of each packet
-  std::vector<WorkList> wl;        // per packet, block ids into the shared table
-  DevBlock *d_blocks = nullptr;    // offsets relative to the packet's first block
+  // Transfer units: runs of consecutive GPU packets, adjacent in the arena,
+  // that a slot copies in, advances and copies back as one (each at least
+  // unit_bytes long, or a single packet when unit_bytes is 0)
+  int64_t unit_bytes = 0;
+  std::vector<int32_t> ustart;     // first packet of each unit, nunits + 1 entries
+  std::vector<int64_t> uhost;      // host element offset of each unit
+  std::vector<int64_t> ulen;       // elements of each unit
+  std::vector<WorkList> wl;        // per unit, block ids into the shared table
+  std::vector<int> uslot;          // slot of each unit: the least loaded so far, in unit order
+  int64_t slot_len = 0;            // elements each slot buffer holds
+  DevBlock *d_blocks = nullptr;    // offsets relative to the first element of the block's unit
   struct Slot {
     hipStream_t stream = nullptr;
     double *state = nullptr;
@@ -1018,7 +1027,6 @@ struct hydro_stream {
     hipEvent_t done = nullptr;
   };
   std::vector<Slot> slots;
-  std::vector<int> pslot;  // slot of each packet: the least loaded so far, in packet order
   hipStream_t ctl = nullptr;
   hipEvent_t ready = nullptr;
   DevTime *d_time = nullptr;
@@ -1050,17 +1058,81 @@ void stream_free(hydro_stream *s) {
   delete s;
 }
 
-// Packets of uneven size: each packet the GPU takes goes to the slot with the
-// fewest bytes so far, so the slot streams finish a step together.
+// Units of uneven size: each unit goes to the slot with the fewest bytes so
+// far, so the slot streams finish a step together.
 void assign_slots(hydro_stream *s) {
-  const int ngpu = (int)s->wl.size() - s->cpu_packets;
   std::vector<int64_t> load(s->slots.size(), 0);
-  s->pslot.assign(s->wl.size(), -1);
-  for (int p = 0; p < ngpu; ++p) {
+  s->uslot.assign(s->ulen.size(), -1);
+  for (size_t u = 0; u < s->ulen.size(); ++u) {
     const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    s->pslot[p] = k;
-    load[k] += s->plen[p];
+    s->uslot[u] = k;
+    load[k] += s->ulen[u];
   }
+}
+
+// The GPU packets [0, npackets - cpu_packets) cut into transfer units; the
+// block table (offsets relative to each block's unit), the units' work lists
+// and, where a unit outgrows them, the slot buffers follow.
+hydro_status build_units(hydro_stream *s) {
+  const int np = (int)s->pstart.size() - 1, ngpu = np - s->cpu_packets;
+  const int nblocks = (int)s->desc.size();
+  s->ustart.clear();
+  s->uhost.clear();
+  s->ulen.clear();
+  for (int p = 0; p < ngpu;) {
+    int q = p + 1;
+    int64_t len = s->plen[p];
+    while (q < ngpu && len * (int64_t)sizeof(double) < s->unit_bytes && s->phost[q] == s->phost[p] + len) len += s->plen[q++];
+    s->ustart.push_back(p);
+    s->uhost.push_back(s->phost[p]);
+    s->ulen.push_back(len);
+    p = q;
+  }
+  s->ustart.push_back(ngpu);
+  const int nu = (int)s->ulen.size();
+  std::vector<hydro_block_desc> local(s->desc);
+  for (int u = 0; u < nu; ++u)
+    for (int b = s->pstart[s->ustart[u]]; b < s->pstart[s->ustart[u + 1]]; ++b) local[b].offset -= s->uhost[u];
+  std::vector<DevBlock> hb(nblocks);
+  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(local.data(), b, s->ndim);
+  if (hipMemcpyAsync(s->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, s->ctl) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->ctl) != hipSuccess)
+    return fail(HYDRO_EDEVICE, "stream: block table upload failed");
+  for (auto &w : s->wl)
+    if (w.d_items) (void)hipFree(w.d_items);
+  s->wl.assign(nu, WorkList());
+  hydro_mesh view;  // descriptors only, for the item builder
+  view.ndim = s->ndim;
+  view.nblocks = nblocks;
+  view.desc = s->desc;
+  for (int u = 0; u < nu; ++u) {
+    std::vector<int32_t> ids;
+    for (int b = s->pstart[s->ustart[u]]; b < s->pstart[s->ustart[u + 1]]; ++b) ids.push_back(b);
+    std::vector<WorkItem> items;
+    int kmask = 0;
+    build_items(&view, ids, {}, items, kmask);
+    hydro_status st = upload_items(items, kmask, s->wl[u], s->ctl);
+    if (st) return st;
+  }
+  int64_t maxlen = 0;
+  for (int64_t l : s->ulen) maxlen = std::max(maxlen, l);
+  if (maxlen > s->slot_len) {
+    for (auto &sl : s->slots) {
+      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+      if (sl.state) (void)hipFree(sl.state);
+      if (sl.u1) (void)hipFree(sl.u1);
+      sl.state = sl.u1 = nullptr;
+    }
+    s->slot_len = 0;
+    for (auto &sl : s->slots)
+      if (hipMalloc(&sl.state, (size_t)maxlen * sizeof(double)) != hipSuccess ||
+          hipMalloc(&sl.u1, (size_t)maxlen * sizeof(double)) != hipSuccess)
+        return fail(HYDRO_ENOMEM, "stream: hipMalloc of a staging slot failed");
+    s->slot_len = maxlen;
+  }
+  assign_slots(s);
+  return HYDRO_OK;
 }
 
 StageArgs slot_args(const hydro_stream *s, const hydro_stream::Slot &sl, const WorkList &wl, int stage, double gamma) {
@@ -1099,7 +1171,6 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
   for (int p = 0; p < npackets; ++p)
     if (packet_start[p + 1] <= packet_start[p]) return fail(HYDRO_EINVAL, "stream: empty or decreasing packet range");
   std::vector<int64_t> phost(npackets), plen(npackets);
-  int64_t maxlen = 0;
   for (int p = 0; p < npackets; ++p) {
     const int b0 = packet_start[p], b1 = packet_start[p + 1];
     int64_t end = blocks[b0].offset;
@@ -1114,7 +1185,6 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
     }
     phost[p] = blocks[b0].offset;
     plen[p] = end - blocks[b0].offset;
-    maxlen = std::max(maxlen, plen[p]);
   }
 
   hydro_stream *s = new hydro_stream();
@@ -1125,12 +1195,6 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
   s->pstart.assign(packet_start, packet_start + npackets + 1);
   s->phost = phost;
   s->plen = plen;
-  // block table with offsets relative to the first block of each block's packet
-  std::vector<hydro_block_desc> local(s->desc);
-  for (int p = 0; p < npackets; ++p)
-    for (int b = packet_start[p]; b < packet_start[p + 1]; ++b) local[b].offset -= phost[p];
-  std::vector<DevBlock> hb(nblocks);
-  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(local.data(), b, ndim);
   auto bail = [&](hydro_status e, const std::string &msg) {
     stream_free(s);
     return fail(e, msg);
@@ -1141,34 +1205,16 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
     return bail(HYDRO_EDEVICE, "stream: control stream creation failed");
   if (hipMalloc(&s->d_blocks, (size_t)nblocks * sizeof(DevBlock)) != hipSuccess)
     return bail(HYDRO_ENOMEM, "stream: hipMalloc of the block table failed");
-  if (hipMemcpyAsync(s->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, s->ctl) !=
-          hipSuccess ||
-      hipStreamSynchronize(s->ctl) != hipSuccess)
-    return bail(HYDRO_EDEVICE, "stream: block table upload failed");
   if (alloc_time(&s->d_time, s->ctl)) return bail(HYDRO_ENOMEM, "stream: time record allocation failed");
-  // work lists: a throwaway mesh view for the item builder (descriptors only)
-  hydro_mesh view;
-  view.ndim = ndim;
-  view.nblocks = nblocks;
-  view.desc = s->desc;
-  s->wl.resize(npackets);
-  for (int p = 0; p < npackets; ++p) {
-    std::vector<int32_t> ids;
-    for (int b = packet_start[p]; b < packet_start[p + 1]; ++b) ids.push_back(b);
-    std::vector<WorkItem> items;
-    int kmask = 0;
-    build_items(&view, ids, {}, items, kmask);
-    if (upload_items(items, kmask, s->wl[p], s->ctl)) return bail(HYDRO_ENOMEM, "stream: work list upload failed");
-  }
   s->slots.resize(nslots);
-  assign_slots(s);
-  for (auto &sl : s->slots) {
+  for (auto &sl : s->slots)
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
       return bail(HYDRO_EDEVICE, "stream: slot stream creation failed");
-    if (hipMalloc(&sl.state, (size_t)maxlen * sizeof(double)) != hipSuccess ||
-        hipMalloc(&sl.u1, (size_t)maxlen * sizeof(double)) != hipSuccess)
-      return bail(HYDRO_ENOMEM, "stream: hipMalloc of a staging slot failed");
+  st = build_units(s);  // one packet per unit; allocates the slot buffers
+  if (st) {
+    stream_free(s);
+    return st;
   }
   *out = s;
   return HYDRO_OK;
@@ -1185,15 +1231,14 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   if (nsteps < 0) return fail(HYDRO_EINVAL, "nsteps must be >= 0");
   if (!finite_pos(cfl)) return fail(HYDRO_EINVAL, "cfl must be finite and > 0");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
-  const int np = (int)s->wl.size();
-  const int ngpu = np - s->cpu_packets;  // packets [ngpu, np) run on the host
+  const int nu = (int)s->ulen.size();  // GPU transfer units; packets past them run on the host
   const bool split = s->cpu_packets > 0;
   const int prec = s->prec;
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   bool good = true;
   const int ns = (int)s->slots.size();
-  std::vector<int> lastp(ns, -1);  // last packet of each slot
-  for (int p = 0; p < ngpu; ++p) lastp[s->pslot[p]] = p;
+  std::vector<int> lastu(ns, -1);  // last unit of each slot
+  for (int u = 0; u < nu; ++u) lastu[s->uslot[u]] = u;
   // every slot stream starts after the control stream's last work
   auto fan_out = [&]() {
     good = good && ok(hipEventRecord(s->ready, s->ctl));
@@ -1203,8 +1248,8 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
     good = good && ok(hipEventRecord(sl.done, sl.stream));
     good = good && ok(hipStreamWaitEvent(s->ctl, sl.done, 0));
   };
-  auto copy_in = [&](int p, hydro_stream::Slot &sl) {
-    good = good && ok(hipMemcpyAsync(sl.state, s->host + s->phost[p], (size_t)s->plen[p] * sizeof(double),
+  auto copy_in = [&](int u, hydro_stream::Slot &sl) {
+    good = good && ok(hipMemcpyAsync(sl.state, s->host + s->uhost[u], (size_t)s->ulen[u] * sizeof(double),
                                      hipMemcpyHostToDevice, sl.stream));
   };
   // the host share: its CFL rate and non-physical flag go into the device
@@ -1220,12 +1265,12 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
   // dt of the first step: rate of every packet's current state
   good = good && ok(hyd::launch_reset(s->d_time, s->ctl));
   fan_out();
-  for (int p = 0; p < ngpu && good; ++p) {
-    auto &sl = s->slots[s->pslot[p]];
-    copy_in(p, sl);
-    good = good && ok(hyd::launch_lambda(s->ndim, is_mixed(prec), s->wl[p].kmask, eos_of(prec), s->wl[p].nitems, sl.stream,
-                                         slot_args(s, sl, s->wl[p], 1, gamma)));
-    if (p == lastp[s->pslot[p]]) done(sl);
+  for (int u = 0; u < nu && good; ++u) {
+    auto &sl = s->slots[s->uslot[u]];
+    copy_in(u, sl);
+    good = good && ok(hyd::launch_lambda(s->ndim, is_mixed(prec), s->wl[u].kmask, eos_of(prec), s->wl[u].nitems, sl.stream,
+                                         slot_args(s, sl, s->wl[u], 1, gamma)));
+    if (u == lastu[s->uslot[u]]) done(sl);
   }
   if (split && good) {
     H.src = s->cpu_un.data();
@@ -1246,20 +1291,20 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
              ok(hipStreamSynchronize(s->ctl));
     }
     std::vector<char> waited(ns, 0);
-    for (int p = 0; p < ngpu && good; ++p) {
-      const int k = s->pslot[p];
+    for (int u = 0; u < nu && good; ++u) {
+      const int k = s->uslot[u];
       auto &sl = s->slots[k];
-      copy_in(p, sl);
+      copy_in(u, sl);
       if (!waited[k]) {
         good = good && ok(hipStreamWaitEvent(sl.stream, s->ready, 0));
         waited[k] = 1;
       }
       for (int stage = 1; stage <= 2; ++stage)
-        good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), stage, s->wl[p].kmask, speeds_of(prec),
-                                            recon_of(prec), eos_of(prec), s->wl[p].nitems, sl.stream,
-                                            slot_args(s, sl, s->wl[p], stage, gamma)));
-      if (p == lastp[k]) done(sl);
-      good = good && ok(hipMemcpyAsync(s->host + s->phost[p], sl.state, (size_t)s->plen[p] * sizeof(double),
+        good = good && ok(hyd::launch_stage(s->ndim, is_mixed(prec), stage, s->wl[u].kmask, speeds_of(prec),
+                                            recon_of(prec), eos_of(prec), s->wl[u].nitems, sl.stream,
+                                            slot_args(s, sl, s->wl[u], stage, gamma)));
+      if (u == lastu[k]) done(sl);
+      good = good && ok(hipMemcpyAsync(s->host + s->uhost[u], sl.state, (size_t)s->ulen[u] * sizeof(double),
                                        hipMemcpyDeviceToHost, sl.stream));
     }
     // a failed earlier step leaves dt NaN: the host share then does nothing either
@@ -1295,7 +1340,7 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
 
 hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, int32_t nthreads) {
   if (!s) return fail(HYDRO_EINVAL, "stream is null");
-  const int np = (int)s->wl.size();
+  const int np = (int)s->pstart.size() - 1;
   if (cpu_packets < 0 || cpu_packets > np) return fail(HYDRO_EINVAL, "cpu_packets must be in 0..npackets");
   if (nthreads < 0) return fail(HYDRO_EINVAL, "nthreads must be >= 0");
   if (cpu_packets > 0 && s->prec != HYDRO_FP64 && s->prec != HYDRO_FP32_FP64)
@@ -1324,8 +1369,14 @@ hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, in
   }
   s->cpu_packets = cpu_packets;
   s->cpu_threads = nthreads > 0 ? nthreads : std::max(1u, std::thread::hardware_concurrency());
-  assign_slots(s);
-  return HYDRO_OK;
+  return build_units(s);
+}
+
+hydro_status hydro_stream_set_unit_bytes(hydro_stream *s, int64_t min_bytes) {
+  if (!s) return fail(HYDRO_EINVAL, "stream is null");
+  if (min_bytes < 0) return fail(HYDRO_EINVAL, "min_bytes must be >= 0");
+  s->unit_bytes = min_bytes;
+  return build_units(s);
 }
 
 }  // extern "C"

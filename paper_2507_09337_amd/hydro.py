@@ -89,6 +89,7 @@ def lib():
             "hydro_stream_run": [vp, i32, dbl, dbl, C.POINTER(C.c_double)],
             "hydro_stream_destroy": [vp],
             "hydro_stream_set_cpu_share": [vp, i32, i32],
+            "hydro_stream_set_unit_bytes": [vp, i64],
             "hydro_step_static": [C.POINTER(BlockDesc), i32, i32, vp, i64, i32, dbl, dbl, vp],
         }
         for name, args in sig.items():
@@ -368,6 +369,11 @@ class HostStream:
         kernel, `nthreads` threads, 0 = all) while the GPU streams the rest."""
         _check(lib().hydro_stream_set_cpu_share(self.h, int(cpu_packets), int(nthreads)),
                "hydro_stream_set_cpu_share")
+
+    def set_unit_bytes(self, min_bytes: int):
+        """Copy and advance consecutive GPU packets together, in units of at
+        least `min_bytes` (0 = one packet per unit, the default)."""
+        _check(lib().hydro_stream_set_unit_bytes(self.h, int(min_bytes)), "hydro_stream_set_unit_bytes")
 
     def close(self):
         if self.h:

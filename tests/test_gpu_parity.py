@@ -391,8 +391,10 @@ def test_timed_run_matches_run_and_reports_step_times():
 # ---------------------------------------------------- host-resident packets
 def test_host_resident_packets_match_device_batch_and_oracle():
     """Packets kept in pinned host memory, streamed through device slots (copy
-    in, two stage launches, copy back on one stream per slot): the result
-    equals the device-resident batch bit for bit and, in FP64, the oracle."""
+    in, two stage launches, copy back on one stream per slot), one packet per
+    transfer unit or consecutive packets merged into units of at least 1 MiB
+    and of at least 64 MiB (all GPU packets in one unit): the result equals
+    the device-resident batch bit for bit and, in FP64, the oracle."""
     import torch
 
     P = I.uneven(nblocks=150, nsteps=8)
@@ -404,13 +406,15 @@ def test_host_resident_packets_match_device_batch_and_oracle():
         t_dev = b.run(P.nsteps, P.cfl, P.gamma)
         U_dev = to_host(arena)
         mesh.close()
-        for nslots in (1, 3):
+        for nslots, unit in ((1, 0), (3, 0), (3, 1 << 20), (2, 64 << 20)):
             host = torch.from_numpy(P.U0.copy()).pin_memory()
             hs = H.HostStream(P.mesh, host, P.packets, prec, nslots)
+            if unit:
+                hs.set_unit_bytes(unit)
             t = hs.run(P.nsteps, P.cfl, P.gamma)
             hs.close()
             U = host.numpy()
-            assert np.array_equal(U, U_dev) and t == t_dev, (prec, nslots)
+            assert np.array_equal(U, U_dev) and t == t_dev, (prec, nslots, unit)
         if prec == H.FP64:
             assert rel_err(P.mesh, U_dev, R) <= TOL64
 

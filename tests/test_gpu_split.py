@@ -36,11 +36,13 @@ def uneven():
     return P, R, t
 
 
-def _stream(P, prec, cpu_packets, nthreads=4, nslots=2, U0=None):
+def _stream(P, prec, cpu_packets, nthreads=4, nslots=2, U0=None, unit=0):
     import torch
 
     host = torch.from_numpy((P.U0 if U0 is None else U0).copy()).pin_memory()
     hs = H.HostStream(P.mesh, host, P.packets, prec, nslots)
+    if unit:
+        hs.set_unit_bytes(unit)
     if cpu_packets:
         hs.set_cpu_share(cpu_packets, nthreads)
     return host, hs
@@ -49,8 +51,9 @@ def _stream(P, prec, cpu_packets, nthreads=4, nslots=2, U0=None):
 def test_split_fp64_bitwise_and_oracle(uneven):
     P, R, t_ref = uneven
     outs = []
-    for k in (0, 5, len(P.packets) // 2, len(P.packets)):
-        host, hs = _stream(P, H.FP64, k)
+    # the last case: GPU packets merged into transfer units of >= 1 MiB
+    for k, unit in ((0, 0), (5, 0), (len(P.packets) // 2, 0), (len(P.packets), 0), (5, 1 << 20)):
+        host, hs = _stream(P, H.FP64, k, unit=unit)
         t = hs.run(P.nsteps, P.cfl, P.gamma)
         hs.close()
         outs.append((host.numpy().copy(), t))
