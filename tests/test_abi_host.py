@@ -111,6 +111,22 @@ def test_bad_ndim_null_arena_and_null_handles():
     assert L.hydro_last_error()  # a message is set
 
 
+def test_empty_inputs_rejected_on_host():
+    """No blocks, no packets, no block ids: EINVAL with a message, before any
+    device call."""
+    m = good()
+    descs = H.descs_from_mesh(m)
+    L = H.lib()
+    h = C.c_void_p()
+    assert L.hydro_mesh_create(descs, 0, 3, FAKE_ARENA, m.arena_len, None, C.byref(h)) == H.EINVAL
+    assert "nblocks" in L.hydro_last_error().decode()
+    ids = (C.c_int32 * 1)(0)
+    assert L.hydro_packet_create(None, ids, 0, 0, C.byref(h)) == H.EINVAL
+    st = (C.c_int32 * 1)(0)
+    assert L.hydro_stream_create(descs, len(descs), 3, FAKE_ARENA, m.arena_len, st, 0, 0, 2, C.byref(h)) == H.EINVAL
+    assert L.hydro_step_static(descs, 0, 3, FAKE_ARENA, m.arena_len, 0, 1e-3, 1.4, None) == H.EINVAL
+
+
 class _Host:
     """Stand-in host arena (never dereferenced: validation fails first)."""
 

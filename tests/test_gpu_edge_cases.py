@@ -14,7 +14,8 @@ tests), mixed FP32/FP64 L1(rho) <= 1e-5.
   * a one-block self-periodic packet through the packet path and the graph
     path;
   * supersonic flow, every x face on the upwind branch of HLLC;
-  * a block at the maximum x extent.
+  * a block at the maximum x extent;
+  * zero steps (graph and host-resident paths): t = 0, the state untouched.
 """
 import numpy as np
 import pytest
@@ -144,3 +145,25 @@ def test_widest_block_accepted():
     """A block at the maximum x extent (16384 cells), eight rows, two planes."""
     mesh = I.block_grid((1, 1, 1), (16384, 8, 2), (0, 0, 0), (1, 8.0 / 16384, 2.0 / 16384), "periodic", 3)
     check_both(mesh, smooth_state(mesh), 3)
+
+
+def test_zero_steps_leave_the_state_untouched():
+    """nsteps = 0 through the graph path and the host-resident path, in both
+    precisions: t = 0 and the state bit for bit as it was."""
+    import torch
+
+    mesh = I.block_grid((2, 2, 2), (16, 16, 16), (0, 0, 0), (1, 1, 1), "periodic", 3)
+    U0 = smooth_state(mesh)
+    for prec in (H.FP64, H.FP32_FP64):
+        arena = to_dev(U0)
+        m = H.Mesh(mesh, arena)
+        b = H.Batch([H.Packet(m, list(range(mesh.nblocks)), prec)])
+        assert b.run(0, CFL, GAMMA) == 0.0
+        assert np.array_equal(to_host(arena), U0)
+        b.close()
+        m.close()
+        host = torch.from_numpy(U0.copy()).pin_memory()
+        hs = H.HostStream(mesh, host, [list(range(mesh.nblocks))], prec, 2)
+        assert hs.run(0, CFL, GAMMA) == 0.0
+        hs.close()
+        assert np.array_equal(host.numpy(), U0)
