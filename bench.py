@@ -35,6 +35,7 @@ import json
 import os
 import sys
 import time
+import types
 
 import numpy as np
 
@@ -100,6 +101,58 @@ def one_step_errors(P, arena, U0_dev, packets_fp64, packets_mixed):
             o, n = int(P.mesh.offset[i]), 5 * int(P.mesh.ncells[i])
             U[o:o + n] = arena[o:o + n].cpu().numpy()
         out[name] = {"max_rel_err": rel_err(P.mesh, U, ref, ids), "l1_rho_rel": l1_rho(P.mesh, U, ref, ids)}
+    return out
+
+
+def gather_blocks(P, arena, ids):
+    """The listed blocks of a device arena, back to back (the layout of
+    P.mesh.subset(ids))."""
+    import torch
+
+    torch.cuda.synchronize()
+    return np.concatenate([arena[int(P.mesh.offset[i]):int(P.mesh.offset[i]) + 5 * int(P.mesh.ncells[i])].cpu().numpy()
+                           for i in ids])
+
+
+class RowCheck:
+    """The error of a throughput row: one step from the initial state, the
+    sampled blocks of the path's result against the oracle's step of a closed
+    mesh around them (the sampled blocks themselves when they are
+    self-contained, else the region that holds their one-step domain of
+    dependence) with the path's own time step and the same method variant."""
+
+    def __init__(self, P, ids, region=None):
+        from oracle import oracle as O
+
+        self.P, self.ids, self._O = P, [int(i) for i in ids], O
+        region = self.ids if region is None else [int(i) for i in region]
+        pos = {g: k for k, g in enumerate(region)}
+        self.m = P.mesh.subset(np.asarray(region))
+        self.U0 = P.mesh.gather(P.U0, np.asarray(region))
+        self.local = [pos[i] for i in self.ids]
+        self.ms = self.m.subset(np.asarray(self.local))
+
+    def err(self, G, dt, speeds=0, recon=0, eos=0):
+        """G: the sampled blocks after one step (gather_blocks layout); dt: the
+        path's time step (its t after that step)."""
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from gpu_util import l1_rho, rel_err
+
+        R = self.U0.copy()
+        self._O.run(self.m, R, 1, self.P.cfl, self.P.gamma, dt, speeds, recon, eos)
+        Rs = self.m.gather(R, np.asarray(self.local))
+        return {"kind": f"one step from the initial state, {len(self.ids)} sampled blocks, vs the oracle with the "
+                        "path's own dt", "dt": dt,
+                "max_rel_err": rel_err(self.ms, G, Rs), "l1_rho_rel": l1_rho(self.ms, G, Rs)}
+
+
+def class_sample(P, per_class=4):
+    """Blocks of every block size, `per_class` of each (seeded)."""
+    rng = np.random.default_rng(1)
+    out = []
+    for n in sorted(set(int(x) for x in P.mesh.n[:, 0])):
+        cand = np.nonzero(P.mesh.n[:, 0] == n)[0]
+        out += sorted(rng.choice(cand, size=min(per_class, cand.size), replace=False).tolist())
     return out
 
 
@@ -460,7 +513,7 @@ def host_packets_bench(args):
                       "paths": out, "cpu_gpu_split": split}), flush=True)
 
 
-def fused_class_study(P, steps, warmup):
+def fused_class_study(P, steps, warmup, check=True):
     """The communication-avoiding fused step on the self-periodic 8^3 blocks
     of the uneven workload: those blocks as their own mesh, advanced by the
     two stage launches (200 algorithmic B per cell-update: U1 written and read
@@ -473,8 +526,12 @@ def fused_class_study(P, steps, warmup):
 
     ids = np.nonzero(P.mesh.n[:, 0] == 8)[0]
     m = P.mesh.subset(ids)
-    U0 = torch.from_numpy(P.mesh.gather(P.U0, ids)).cuda()
+    U0h = P.mesh.gather(P.U0, ids)
+    U0 = torch.from_numpy(U0h).cuda()
     cells = m.total_cells
+    sub = types.SimpleNamespace(mesh=m, U0=U0h, gamma=P.gamma, cfl=P.cfl)
+    chk = RowCheck(sub, np.random.default_rng(2).choice(m.nblocks, size=min(8, m.nblocks), replace=False)) \
+        if check else None
     out = {"blocks": int(ids.size), "cells": int(cells)}
     for prec, pname in ((H.FP32_FP64, "mixed"), (H.FP64, "fp64")):
         for fused in (False, True):
@@ -493,17 +550,28 @@ def fused_class_study(P, steps, warmup):
                 "achieved_gbs": alg * cells / (dev * 1e-3) / 1e9,
                 "frac_of_hbm": alg * cells / (dev * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "gbs_at_200B": 200.0 * cells / (dev * 1e-3) / 1e9}
+            if chk is not None:
+                arena.copy_(U0)
+                b2 = H.Batch([H.Packet(mesh, range(m.nblocks), prec)])
+                if fused:
+                    b2.set_tiling(8, 5)
+                dt = b2.run(1, P.cfl, P.gamma)
+                b2.close()
+                out[f"{pname}_{'fused' if fused else 'two_launch'}"]["errors_vs_oracle"] = \
+                    chk.err(gather_blocks(sub, arena, chk.ids), dt)
             mesh.close()
             log("fused study", pname, fused, json.dumps(out[f"{pname}_{'fused' if fused else 'two_launch'}"]))
     return out
 
 
-def secondary_paths(steps, warmup):
+def secondary_paths(steps, warmup, check=True):
     """The uneven workload (6000 self-periodic blocks of 8^3/16^3/32^3, 147
     packets): the batched mixed and FP64 paths with the default tiling, the
     fused step of its 8^3 class, and its state held in pinned host memory
     (four GPU staging slots; GPU only, and with the last 8 packets on the host
-    cores).  Reported beside the headline, never as `value`."""
+    cores).  Each row carries its error after one step from the initial state
+    on sampled blocks of every size.  Reported beside the headline, never as
+    `value`."""
     import torch
 
     from paper_2507_09337_amd import hydro as H
@@ -515,6 +583,7 @@ def secondary_paths(steps, warmup):
     log(f"secondary workload {P.name}: {P.mesh.nblocks} blocks, {cells} cells, built in {time.perf_counter() - t0:.1f} s")
     out = {"workload": f"uneven: {P.mesh.nblocks} self-periodic blocks of 8^3/16^3/32^3, {cells} cells, "
                        f"{len(P.packets)} packets, gamma {P.gamma}, CFL {P.cfl}", "steps": steps}
+    chk = RowCheck(P, class_sample(P)) if check else None
     U0 = torch.from_numpy(P.U0).cuda()
     arena = U0.clone()
     mesh = H.Mesh(P.mesh, arena)
@@ -529,11 +598,17 @@ def secondary_paths(steps, warmup):
         b.close()
         out[name] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
                      "device_ms_per_step": float(np.mean(ms))}
+        if chk is not None:
+            arena.copy_(U0)
+            b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+            dt = b.run(1, P.cfl, P.gamma)
+            b.close()
+            out[name]["errors_vs_oracle"] = chk.err(gather_blocks(P, arena, chk.ids), dt)
         log("secondary", name, json.dumps(out[name]))
     mesh.close()
     del arena, U0
     torch.cuda.empty_cache()
-    out["fused_8cube_class"] = fused_class_study(P, steps, warmup)
+    out["fused_8cube_class"] = fused_class_study(P, steps, warmup, check)
     nthreads = len(os.sched_getaffinity(0))
     for k in (0, 8):
         host = torch.from_numpy(P.U0.copy()).pin_memory()
@@ -551,6 +626,17 @@ def secondary_paths(steps, warmup):
                     "unit_bytes": HOST_UNIT_BYTES,
                     "note": "PCIe-inclusive (state in pinned host memory); four staging slots; consecutive GPU "
                             "packets copied and advanced in transfer units of at least unit_bytes"}
+        if chk is not None:  # one step from the initial state through the same stream set-up
+            host = torch.from_numpy(P.U0.copy()).pin_memory()
+            hs = H.HostStream(P.mesh, host, P.packets, H.FP32_FP64, 4)
+            hs.set_unit_bytes(HOST_UNIT_BYTES)
+            hs.set_cpu_share(k, nthreads)
+            dt = hs.run(1, P.cfl, P.gamma)
+            hs.close()
+            Uh = host.numpy()
+            G = np.concatenate([Uh[int(P.mesh.offset[i]):int(P.mesh.offset[i]) + 5 * int(P.mesh.ncells[i])]
+                                for i in chk.ids])
+            out[key]["errors_vs_oracle"] = chk.err(G, dt)
         log("secondary", key, json.dumps(out[key]))
     return out
 
@@ -726,19 +812,36 @@ def main():
 
     # method variants (Einfeldt, PVRS wave speeds; conserved, characteristic PLM; gas + radiation EOS):
     # kernel time of a few eager steps
+    # each row's error: one step from the initial state on sampled blocks against the oracle with the same
+    # method variant
+    check = None
+    if not args.no_check:  # sampled blocks: the centred subset where the workload has one
+        sub = P.meta.get("subset")
+        reg = region_around(P, 1) if sub is not None else None
+        check = RowCheck(P, sub, reg) if reg is not None else RowCheck(P, sample_blocks(P), None) \
+            if P.name == "uneven" else None
     variants = {}
-    for name, prec in (("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT), ("fp64_einfeldt", H.FP64 | H.EINFELDT),
-                       ("mixed_pvrs", H.FP32_FP64 | H.PVRS), ("fp64_pvrs", H.FP64 | H.PVRS),
-                       ("mixed_conserved", H.FP32_FP64 | H.CONSERVED), ("fp64_conserved", H.FP64 | H.CONSERVED),
-                       ("mixed_characteristic", H.FP32_FP64 | H.CHARACTERISTIC),
-                       ("fp64_characteristic", H.FP64 | H.CHARACTERISTIC),
-                       ("fp64_gas_radiation", H.FP64 | H.GAS_RADIATION)):
+    for name, prec, opts in (
+            ("mixed_einfeldt", H.FP32_FP64 | H.EINFELDT, (O.EINFELDT, 0, 0)),
+            ("fp64_einfeldt", H.FP64 | H.EINFELDT, (O.EINFELDT, 0, 0)),
+            ("mixed_pvrs", H.FP32_FP64 | H.PVRS, (O.PVRS, 0, 0)), ("fp64_pvrs", H.FP64 | H.PVRS, (O.PVRS, 0, 0)),
+            ("mixed_conserved", H.FP32_FP64 | H.CONSERVED, (0, O.CONSERVED, 0)),
+            ("fp64_conserved", H.FP64 | H.CONSERVED, (0, O.CONSERVED, 0)),
+            ("mixed_characteristic", H.FP32_FP64 | H.CHARACTERISTIC, (0, O.CHARACTERISTIC, 0)),
+            ("fp64_characteristic", H.FP64 | H.CHARACTERISTIC, (0, O.CHARACTERISTIC, 0)),
+            ("fp64_gas_radiation", H.FP64 | H.GAS_RADIATION, (0, 0, O.GAS_RADIATION))):
         arena.copy_(U0_dev)
         b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
         k = b.time_kernels(min(args.steps, 5), P.cfl, P.gamma)
         b.close()
         variants[name] = {"stage_ms_per_step": k["stage1_ms"] + k["stage2_ms"],
                           "cell_updates_per_s": cells / ((k["stage1_ms"] + k["stage2_ms"]) * 1e-3)}
+        if check is not None:
+            arena.copy_(U0_dev)
+            b = H.Batch([H.Packet(mesh, ids, prec) for ids in P.packets])
+            dt = b.run(1, P.cfl, P.gamma)
+            b.close()
+            variants[name]["errors_vs_oracle"] = check.err(gather_blocks(P, arena, check.ids), dt, *opts)
         log(name, json.dumps(variants[name]))
 
     if not args.no_plain:
@@ -758,6 +861,11 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - ts
         results["plain_fp64"] = {"cell_updates_per_s": cells * args.steps / el, "ms_per_step": 1e3 * el / args.steps}
+        if check is not None:
+            arena.copy_(U0_dev)
+            dt = min(pk.reduce_dt(P.gamma, P.cfl) for pk in pk64)
+            b.advance_plain(dt, P.gamma)
+            results["plain_fp64"]["errors_vs_oracle"] = check.err(gather_blocks(P, arena, check.ids), dt)
         b.close()
         log("plain_fp64", json.dumps(results["plain_fp64"]))
 
@@ -872,7 +980,7 @@ def main():
         del arena, U0_dev
         mesh.close()
         torch.cuda.empty_cache()
-        line["secondary"] = secondary_paths(min(args.steps, 10), min(args.warmup, 2))
+        line["secondary"] = secondary_paths(min(args.steps, 10), min(args.warmup, 2), not args.no_check)
     print(json.dumps(line), flush=True)
 
 
