@@ -386,7 +386,8 @@ hydro_status hydro_stream_run(hydro_stream *s, int32_t nsteps, double cfl, doubl
  * into the device accumulator before the dt update; failures follow
  * hydro_stream_run's contract.  A stream whose precision code carries a
  * method variant takes no host share (EINVAL); on a mixed-precision stream
- * the host packets still compute in FP64.  Errors: EINVAL, ENOMEM. */
+ * the host packets still compute in FP64.  On an error the stream keeps
+ * its previous split.  Errors: EINVAL, ENOMEM, EDEVICE. */
 hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, int32_t nthreads);
 
 /* Transfer granularity of a stream (the paper's packet size knob, Sec. 6.1:
@@ -396,8 +397,9 @@ hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, in
  * units of at least min_bytes each (the last unit may be smaller; a single
  * packet larger than min_bytes is a unit of its own); min_bytes = 0, the
  * default, keeps one packet per unit.  The staging slots grow to the
- * largest unit.  Results are the same bit for bit at any setting.  Errors:
- * EINVAL, ENOMEM, EDEVICE. */
+ * largest unit.  Results are the same bit for bit at any setting.  On an
+ * error the stream keeps its previous units and buffers.  Errors: EINVAL,
+ * ENOMEM, EDEVICE. */
 hydro_status hydro_stream_set_unit_bytes(hydro_stream *s, int64_t min_bytes);
 
 hydro_status hydro_stream_destroy(hydro_stream *s);

@@ -1070,67 +1070,97 @@ void assign_slots(hydro_stream *s) {
   }
 }
 
-// The GPU packets [0, npackets - cpu_packets) cut into transfer units; the
-// block table (offsets relative to each block's unit), the units' work lists
-// and, where a unit outgrows them, the slot buffers follow.
-hydro_status build_units(hydro_stream *s) {
-  const int np = (int)s->pstart.size() - 1, ngpu = np - s->cpu_packets;
+// The GPU packets [0, npackets - cpu_packets) cut into transfer units of at
+// least unit_bytes; the block table (offsets relative to each block's unit),
+// the units' work lists and, where a unit outgrows them, the slot buffers
+// follow.  All or nothing: on an error the stream keeps its previous units,
+// buffers and table, and the caller keeps its previous settings.
+hydro_status build_units(hydro_stream *s, int64_t unit_bytes, int cpu_packets) {
+  const int np = (int)s->pstart.size() - 1, ngpu = np - cpu_packets;
   const int nblocks = (int)s->desc.size();
-  s->ustart.clear();
-  s->uhost.clear();
-  s->ulen.clear();
+  std::vector<int32_t> ustart;
+  std::vector<int64_t> uhost, ulen;
   for (int p = 0; p < ngpu;) {
     int q = p + 1;
     int64_t len = s->plen[p];
-    while (q < ngpu && len * (int64_t)sizeof(double) < s->unit_bytes && s->phost[q] == s->phost[p] + len) len += s->plen[q++];
-    s->ustart.push_back(p);
-    s->uhost.push_back(s->phost[p]);
-    s->ulen.push_back(len);
+    while (q < ngpu && len * (int64_t)sizeof(double) < unit_bytes && s->phost[q] == s->phost[p] + len)
+      len += s->plen[q++];
+    ustart.push_back(p);
+    uhost.push_back(s->phost[p]);
+    ulen.push_back(len);
     p = q;
   }
-  s->ustart.push_back(ngpu);
-  const int nu = (int)s->ulen.size();
-  std::vector<hydro_block_desc> local(s->desc);
-  for (int u = 0; u < nu; ++u)
-    for (int b = s->pstart[s->ustart[u]]; b < s->pstart[s->ustart[u + 1]]; ++b) local[b].offset -= s->uhost[u];
-  std::vector<DevBlock> hb(nblocks);
-  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(local.data(), b, s->ndim);
-  if (hipMemcpyAsync(s->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, s->ctl) !=
-          hipSuccess ||
-      hipStreamSynchronize(s->ctl) != hipSuccess)
-    return fail(HYDRO_EDEVICE, "stream: block table upload failed");
-  for (auto &w : s->wl)
-    if (w.d_items) (void)hipFree(w.d_items);
-  s->wl.assign(nu, WorkList());
+  ustart.push_back(ngpu);
+  const int nu = (int)ulen.size();
+  // new work lists and, if needed, larger slot buffers, before anything is replaced
+  std::vector<WorkList> wl(nu);
+  std::vector<std::pair<double *, double *>> bufs;
+  auto drop = [&]() {
+    for (auto &w : wl)
+      if (w.d_items) (void)hipFree(w.d_items);
+    for (auto &pr : bufs) {
+      if (pr.first) (void)hipFree(pr.first);
+      if (pr.second) (void)hipFree(pr.second);
+    }
+  };
   hydro_mesh view;  // descriptors only, for the item builder
   view.ndim = s->ndim;
   view.nblocks = nblocks;
   view.desc = s->desc;
   for (int u = 0; u < nu; ++u) {
     std::vector<int32_t> ids;
-    for (int b = s->pstart[s->ustart[u]]; b < s->pstart[s->ustart[u + 1]]; ++b) ids.push_back(b);
+    for (int b = s->pstart[ustart[u]]; b < s->pstart[ustart[u + 1]]; ++b) ids.push_back(b);
     std::vector<WorkItem> items;
     int kmask = 0;
     build_items(&view, ids, {}, items, kmask);
-    hydro_status st = upload_items(items, kmask, s->wl[u], s->ctl);
-    if (st) return st;
+    hydro_status st = upload_items(items, kmask, wl[u], s->ctl);
+    if (st) {
+      drop();
+      return st;
+    }
   }
   int64_t maxlen = 0;
-  for (int64_t l : s->ulen) maxlen = std::max(maxlen, l);
+  for (int64_t l : ulen) maxlen = std::max(maxlen, l);
   if (maxlen > s->slot_len) {
-    for (auto &sl : s->slots) {
-      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    bufs.assign(s->slots.size(), {nullptr, nullptr});
+    for (auto &pr : bufs)
+      if (hipMalloc(&pr.first, (size_t)maxlen * sizeof(double)) != hipSuccess ||
+          hipMalloc(&pr.second, (size_t)maxlen * sizeof(double)) != hipSuccess) {
+        drop();
+        return fail(HYDRO_ENOMEM, "stream: hipMalloc of a staging slot failed");
+      }
+  }
+  std::vector<hydro_block_desc> local(s->desc);
+  for (int u = 0; u < nu; ++u)
+    for (int b = s->pstart[ustart[u]]; b < s->pstart[ustart[u + 1]]; ++b) local[b].offset -= uhost[u];
+  std::vector<DevBlock> hb(nblocks);
+  for (int b = 0; b < nblocks; ++b) hb[b] = make_devblock(local.data(), b, s->ndim);
+  for (auto &sl : s->slots)  // no copy or launch of the old set-up may still use the table
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+  if (hipMemcpyAsync(s->d_blocks, hb.data(), hb.size() * sizeof(DevBlock), hipMemcpyHostToDevice, s->ctl) !=
+          hipSuccess ||
+      hipStreamSynchronize(s->ctl) != hipSuccess) {
+    drop();
+    return fail(HYDRO_EDEVICE, "stream: block table upload failed");
+  }
+  // commit
+  for (auto &w : s->wl)
+    if (w.d_items) (void)hipFree(w.d_items);
+  s->wl.swap(wl);
+  if (!bufs.empty()) {
+    for (size_t k = 0; k < s->slots.size(); ++k) {
+      auto &sl = s->slots[k];
       if (sl.state) (void)hipFree(sl.state);
       if (sl.u1) (void)hipFree(sl.u1);
-      sl.state = sl.u1 = nullptr;
+      sl.state = bufs[k].first;
+      sl.u1 = bufs[k].second;
     }
-    s->slot_len = 0;
-    for (auto &sl : s->slots)
-      if (hipMalloc(&sl.state, (size_t)maxlen * sizeof(double)) != hipSuccess ||
-          hipMalloc(&sl.u1, (size_t)maxlen * sizeof(double)) != hipSuccess)
-        return fail(HYDRO_ENOMEM, "stream: hipMalloc of a staging slot failed");
     s->slot_len = maxlen;
   }
+  s->ustart.swap(ustart);
+  s->uhost.swap(uhost);
+  s->ulen.swap(ulen);
+  s->unit_bytes = unit_bytes;
   assign_slots(s);
   return HYDRO_OK;
 }
@@ -1211,7 +1241,7 @@ hydro_status hydro_stream_create(const hydro_block_desc *blocks, int32_t nblocks
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
       return bail(HYDRO_EDEVICE, "stream: slot stream creation failed");
-  st = build_units(s);  // one packet per unit; allocates the slot buffers
+  st = build_units(s, 0, 0);  // one packet per unit; allocates the slot buffers
   if (st) {
     stream_free(s);
     return st;
@@ -1354,6 +1384,9 @@ hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, in
   } catch (...) {
     return fail(HYDRO_ENOMEM, "host first-stage buffer allocation failed");
   }
+  // the GPU's units first: on an error the stream keeps its previous split
+  hydro_status st = build_units(s, s->unit_bytes, cpu_packets);
+  if (st) return st;
   s->cpu_u1.swap(u1);
   s->cpu_un.assign(nb, nullptr);
   s->cpu_u1p.assign(nb, nullptr);
@@ -1369,14 +1402,13 @@ hydro_status hydro_stream_set_cpu_share(hydro_stream *s, int32_t cpu_packets, in
   }
   s->cpu_packets = cpu_packets;
   s->cpu_threads = nthreads > 0 ? nthreads : std::max(1u, std::thread::hardware_concurrency());
-  return build_units(s);
+  return HYDRO_OK;
 }
 
 hydro_status hydro_stream_set_unit_bytes(hydro_stream *s, int64_t min_bytes) {
   if (!s) return fail(HYDRO_EINVAL, "stream is null");
   if (min_bytes < 0) return fail(HYDRO_EINVAL, "min_bytes must be >= 0");
-  s->unit_bytes = min_bytes;
-  return build_units(s);
+  return build_units(s, min_bytes, s->cpu_packets);
 }
 
 }  // extern "C"
