@@ -545,13 +545,13 @@ hydro_status nonphys(const DevTime &h) {
                                   (h.bad_block != INT_MAX ? " in block " + std::to_string(h.bad_block) : std::string()));
 }
 
+// The batch's work list and fused-block list from its tiling settings, all
+// or nothing: on an error the batch keeps its previous lists.
 hydro_status rebuild_batch_items(hydro_batch *b) {
   std::vector<WorkItem> items;
   std::vector<int32_t> fused;
   int kmask = 0;
   build_items(b->m, b->ids, b->cfg, items, kmask, &fused);
-  hydro_status st = upload_items(items, kmask, b->wl, b->m->stream);
-  if (st) return st;
   int32_t *d = nullptr;
   if (!fused.empty()) {
     if (hipMalloc(&d, fused.size() * sizeof(int32_t)) != hipSuccess)
@@ -564,6 +564,14 @@ hydro_status rebuild_batch_items(hydro_batch *b) {
       return fail(HYDRO_EDEVICE, std::string("fused block list upload: ") + hipGetErrorString(e));
     }
   }
+  WorkList wl;
+  hydro_status st = upload_items(items, kmask, wl, b->m->stream);
+  if (st) {
+    if (d) (void)hipFree(d);
+    return st;
+  }
+  if (b->wl.d_items) (void)hipFree(b->wl.d_items);
+  b->wl = wl;
   if (b->d_fused) (void)hipFree(b->d_fused);
   b->d_fused = d;
   b->nfused = (int)fused.size();
@@ -1435,8 +1443,11 @@ hydro_status hydro_batch_set_tiling(hydro_batch *b, int32_t edge, int32_t tile, 
   TileCfg c;
   c.tile = tile;
   c.zchunk = zchunk;
+  const auto prev = b->cfg;
   b->cfg[edge] = c;
-  return rebuild_batch_items(b);
+  hydro_status st = rebuild_batch_items(b);
+  if (st) b->cfg = prev;  // the work list in use still follows the previous settings
+  return st;
 }
 
 hydro_status hydro_batch_set_launch(hydro_batch *b, int32_t grid, int32_t xcd_remap) {
