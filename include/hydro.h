@@ -305,9 +305,10 @@ hydro_status hydro_batch_destroy(hydro_batch *b);
  * fastest, then picks grid and xcd_remap the same way; a class the fused
  * step can take gets it when its full step on a copy of the sample matches
  * the default tiling's and the whole batch step (all launches) is faster
- * with it.  reps = timed launches per candidate
- * (>= 1).  Synchronising.  hydro_batch_set_occupancy(b, waves) asks the
- * stage kernels of the batch's launches for the register budget of `waves`
+ * with it.  reps = timed launches per candidate (>= 1).  Synchronising; on
+ * an error the batch keeps the tiling, launch and occupancy it had before
+ * the call (set_tiling likewise).  hydro_batch_set_occupancy(b, waves) asks
+ * the stage kernels of the batch's launches for the register budget of `waves`
  * (2, 3 or 4) waves per SIMD instead of their own (0); only for HYDRO_FP64 or
  * HYDRO_FP32_FP64 without variants (EINVAL otherwise); the autotuner tries 2,
  * 3 and 4 after the launch shape, parity-checked like the tilings.

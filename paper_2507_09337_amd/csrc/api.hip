@@ -1756,10 +1756,27 @@ static hydro_status time_full(hydro_batch *b, double gamma, int reps, double &ms
   return HYDRO_OK;
 }
 
+static hydro_status autotune(hydro_batch *b, double gamma, int32_t reps);
+
 hydro_status hydro_batch_autotune(hydro_batch *b, double gamma, int32_t reps) {
   if (!b) return fail(HYDRO_EINVAL, "batch is null");
   if (reps < 1) return fail(HYDRO_EINVAL, "reps must be >= 1");
   if (!std::isfinite(gamma) || gamma <= 1.0) return fail(HYDRO_EINVAL, "gamma must be finite and > 1");
+  const auto cfg = b->cfg;
+  const int grid = b->grid, remap = b->remap, occ = b->occ;
+  hydro_status st = autotune(b, gamma, reps);
+  if (st) {  // back to the settings the batch had (its message kept)
+    const std::string msg = g_err;
+    b->cfg = cfg;
+    (void)rebuild_batch_items(b);
+    (void)hydro_batch_set_launch(b, grid, remap);
+    (void)hydro_batch_set_occupancy(b, occ);
+    std::snprintf(g_err, sizeof(g_err), "%s", msg.c_str());
+  }
+  return st;
+}
+
+static hydro_status autotune(hydro_batch *b, double gamma, int32_t reps) {
   hydro_mesh *m = b->m;
   const double tol = is_mixed(b->prec) ? 1e-6 : 1e-13;
   std::vector<int> fused_ok;  // classes whose fused step passed the parity check
