@@ -1511,7 +1511,9 @@ hydro_status hydro_batch_get_config(hydro_batch *b, int32_t *out, int32_t nclass
         tile = TILE_FUSED;
       } else if (can16 && c.tile != 1) {
         const bool whole = b->m->ndim == 3 && (c.zchunk == 0 || (any && c.zchunk >= any->n[2]));
-        const int run = !whole ? 1 : (c.tile < 0 ? default_run(b->m, tiles[kv.first]) : std::max(c.tile, 1));
+        // runs chain blocks along their +z links: a class without them runs single blocks
+        const bool zlinked = any && any->face_kind[5] == HYDRO_NBR;
+        const int run = !whole || !zlinked ? 1 : (c.tile < 0 ? default_run(b->m, tiles[kv.first]) : std::max(c.tile, 1));
         tile = run > 1 ? run : 0;
       }
       out[3 + 4 * k + 1] = tile;
@@ -1802,7 +1804,9 @@ static hydro_status autotune(hydro_batch *b, double gamma, int32_t reps) {
         cands.push_back(c);
       }
     }
-    if (can16 && m->ndim == 3)
+    bool zlinked = true;  // z-runs chain blocks along their +z links
+    for (int id : ids) zlinked = zlinked && m->desc[id].face_kind[5] == HYDRO_NBR;
+    if (can16 && m->ndim == 3 && zlinked)
       for (int k : {2, 4}) {
         TileCfg c;
         c.tile = k;
