@@ -111,6 +111,36 @@ def test_bad_ndim_null_arena_and_null_handles():
     assert L.hydro_last_error()  # a message is set
 
 
+def test_every_handle_call_rejects_a_null_handle():
+    """Each call that takes a packet, batch or stream handle returns EINVAL
+    with a message for a null handle, before any device call."""
+    L = H.lib()
+    d = C.c_double()
+    i = C.c_int32()
+    cfg = (C.c_int32 * 64)()
+    calls = {
+        "hydro_packet_reduce_dt": (None, 1.4, 0.4, C.byref(d)),
+        "hydro_packet_destroy": (None,),
+        "hydro_batch_advance_plain": (None, 1e-3, 1.4),
+        "hydro_batch_run_timed": (None, 1, 0.4, 1.4, None, C.byref(d)),
+        "hydro_batch_time_kernels": (None, 1, 0.4, 1.4, C.byref(d)),
+        "hydro_batch_set_tiling": (None, 16, 16, 0),
+        "hydro_batch_set_launch": (None, 0, 1),
+        "hydro_batch_set_occupancy": (None, 3),
+        "hydro_batch_autotune": (None, 1.4, 1),
+        "hydro_batch_get_config": (None, cfg, 16, C.byref(i)),
+        "hydro_batch_destroy": (None,),
+        "hydro_stream_run": (None, 1, 0.4, 1.4, None),
+        "hydro_stream_set_cpu_share": (None, 1, 1),
+        "hydro_stream_set_unit_bytes": (None, 1 << 20),
+        "hydro_stream_destroy": (None,),
+    }
+    for name, args in calls.items():
+        L.hydro_last_error()
+        assert getattr(L, name)(*args) == H.EINVAL, name
+        assert L.hydro_last_error(), name
+
+
 def test_empty_inputs_rejected_on_host():
     """No blocks, no packets, no block ids: EINVAL with a message, before any
     device call."""
